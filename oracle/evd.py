@@ -1,0 +1,425 @@
+"""The EVD multicomponent LBM with forcing, written plainly in torch float64.
+
+Lattice units throughout: delta_x = delta_t = 1 (Sec. 4 opening).
+Population tensors have shape [N, Q, nz, ny, nx] (species, direction, z, y, x);
+2-D lattices use nz = 1.  Species are ordered by ascending molar mass and the
+masses are normalised so that M_1 = 1, hence c_1 = 1 (Sec. 4 opening).
+
+One time step is  f(t) --collide--> f~(t) --stream + walls--> f(t+1):
+  * collide: eq. (LBE_forcing) with Omega = Omega^ii + sum_j Omega^ij
+    (eqs. BGK_self_collision, Cross_collision_Sirovich), the equilibria of
+    eq. (feqi0) and the one after it, and the standard forcing term of
+    eq. (CE_forcing_term_discretized); the moments entering them are eqs.
+    (zeroth_order_moment), (first_order_moment_force), (Sirovich_mixture_density)
+    and (Sirovich_mixture_velocity); tau_ij solves eq. (relation_tauij_diff_coeff)
+    at every node (Sec. 4.1).
+  * stream: eq. (Second_order_spatial_interpolation), read as quadratic Lagrange
+    interpolation of the post-collision values of the 3x3 (3x3x3) neighbourhood
+    at the departure point, then the impermeable-wall scheme of Appendix A.
+
+Readings taken where the paper is silent (each repeated at its function):
+  R1 the primed points of the interpolation formula are the landing positions
+     of the neighbours' post-collision populations, with A = (+1,0), B = (0,+1),
+     C = (-1,0), D = (0,-1), E = (+1,+1), F = (-1,+1), G = (-1,-1), H = (+1,-1)
+     as source offsets from the target O (the only labelling under which c = 1
+     is an exact shift and Appendix A's right wall has its solid node at A);
+  R2 the wall scheme of Appendix A, stated per wall and per direction there,
+     is applied as one rule for any single wall axis, 2-D or 3-D;
+  R3 for N > 3 species the tau relation is solved with the index convention of
+     the paper's ternary solution: for the pair i < j the sum runs over
+     rho_s / tau_sj;
+  R4 a species with rho_i = 0 at a node takes u_i^eq = F_i/(2 rho_i) -> k_i/2
+     (any finite value gives the same populations, as everything it enters is
+     multiplied by rho_i);
+  R5 pressure p = n M_1 c_{s,1}^2 with c_{s,1}^2 = 1/3 (standard D2Q9 value).
+"""
+import math
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+from .lattice import Lattice, DTYPE
+
+AXIS_DIM = {0: -1, 1: -2, 2: -3}   # x, y, z -> spatial tensor dimension
+
+
+def lagrange_weights(s):
+    """1-D weights (lambda_-1, lambda_0, lambda_+1) of the source nodes at
+    offsets -1, 0, +1 from the target, for Courant number s.
+
+    They are the one-dimensional factors of eq. (Second_order_spatial_
+    interpolation): the coefficient of C' is xi(1+xi)/2, of O' is 1-xi^2 and of
+    A' is -xi(1-xi)/2 (reading R1)."""
+    return (s * (1.0 + s) / 2.0, 1.0 - s * s, -s * (1.0 - s) / 2.0)
+
+
+@dataclass
+class Model:
+    """Problem statement of the method (Sec. 4.1 and 4.2): lattice, species
+    molar masses, pair diffusivities D_ij (lattice units), tau_1 (viscosity),
+    specific body force k (F_i = rho_i k, eq. MS_equation), and per-axis
+    impermeable walls (Appendix A) or periodicity."""
+    lattice: str
+    nx: int
+    ny: int
+    nz: int
+    masses: Sequence[float]
+    diff: torch.Tensor                  # [N, N] symmetric, lattice units
+    tau1: float
+    g: torch.Tensor = None              # [3] specific force (gravity)
+    walls: Sequence[bool] = (False, False, False)
+    n0: Optional[float] = None
+    force_field: Optional[torch.Tensor] = None   # [3, nz, ny, nx] overrides g
+
+    def __post_init__(self):
+        self.lat = Lattice(self.lattice)
+        self.N = len(self.masses)
+        if list(self.masses) != sorted(self.masses):
+            raise ValueError("species must be ordered by ascending molar mass")
+        m1 = float(self.masses[0])
+        # Sec. 4 opening: M_1 = 1 for the lightest species.
+        self.M = [float(m) / m1 for m in self.masses]
+        self.diff = torch.as_tensor(self.diff, dtype=DTYPE)
+        if self.g is None:
+            self.g = torch.zeros(3, dtype=DTYPE)
+        self.g = torch.as_tensor(self.g, dtype=DTYPE)
+        if self.lat.dim == 2 and self.nz != 1:
+            raise ValueError("2-D lattice needs nz = 1")
+        if sum(bool(w) for w in self.walls) > 1:
+            raise ValueError("walls on more than one axis are not supported")
+        for a, w in enumerate(self.walls):
+            if w and self.shape_axis(a) < 2:
+                raise ValueError("a wall axis needs at least 2 nodes")
+        if self.lat.dim == 2 and self.walls[2]:
+            raise ValueError("no z walls in 2-D")
+
+    def shape_axis(self, a):
+        return (self.nx, self.ny, self.nz)[a]
+
+    # ---------------------------------------------------------------- S0
+    def speeds(self):
+        """c_i = sqrt(M_1/M_i), eq. (speed_DLS) with c_1 = 1."""
+        return [math.sqrt(1.0 / m) for m in self.M]
+
+    def sound2(self):
+        """c_{s,i}^2 = c_i^2 / 3 (reading R5 applied per species via eq. speed_DLS)."""
+        return [c * c / 3.0 for c in self.speeds()]
+
+    def taus(self):
+        """tau_i from nu_i = (tau_i - 1/2) c_{s,i}^2 equal for all species
+        (Sec. 3, after eq. epecies_momentum_eq; Sec. 4 opening)."""
+        return [0.5 + (self.tau1 - 0.5) * m for m in self.M]
+
+    def velocities(self):
+        """e^i_alpha = c_i * integer direction, eq. (discrete_velocity_DLS).
+        Returns [N, Q, 3]."""
+        c = torch.tensor(self.speeds(), dtype=DTYPE)
+        return c[:, None, None] * self.lat.c[None, :, :]
+
+    def accel(self):
+        """Specific force k at every node, [3, nz, ny, nx]."""
+        if self.force_field is not None:
+            return self.force_field.to(DTYPE)
+        return self.g[:, None, None, None].expand(3, self.nz, self.ny, self.nx)
+
+    def default_n0(self):
+        """Total mole number of the initial state: n = sum_i x_i rho_i0 / M_i
+        (Sec. 4.1) with ideal pure densities rho_i0 = M_i / M_max, i.e. the
+        heaviest pure species has rho = 1 (Sec. 4 opening).  Then n = 1/M_max
+        whatever the composition."""
+        return 1.0 / max(self.M) if self.n0 is None else float(self.n0)
+
+
+def _dot(a, b):
+    """Sum over the last component axis of [..., 3]-shaped factors."""
+    return (a * b).sum(dim=-1)
+
+
+# -------------------------------------------------------------------- moments
+def species_moments(model, f):
+    """rho_i (eq. zeroth_order_moment) and u_i^eq with the force shift
+    (eq. first_order_moment_force):  u_i^eq = (sum_a e f)/rho_i + F_i/(2 rho_i),
+    F_i = rho_i k.  Reading R4 for rho_i = 0.
+
+    Returns rho [N, nz, ny, nx] and ueq [N, nz, ny, nx, 3]."""
+    e = model.velocities()                                 # [N, Q, 3]
+    rho = f.sum(dim=1)
+    mom = torch.einsum("nqc,nqzyx->nzyxc", e, f)
+    k = model.accel().permute(1, 2, 3, 0)[None]            # [1, nz, ny, nx, 3]
+    safe = torch.where(rho == 0, torch.ones_like(rho), rho)
+    ueq = torch.where((rho == 0)[..., None], 0.5 * k.expand_as(mom),
+                      mom / safe[..., None] + 0.5 * k)
+    return rho, ueq
+
+
+def mixture(model, rho_i, ueq):
+    """rho = sum rho_i (eq. Sirovich_mixture_density),
+    u = sum w_i u_i^eq with w_i = rho_i/rho (eq. Sirovich_mixture_velocity),
+    n = sum rho_i/M_i (Sec. 3, after eq. CE_EQ102) and p = n M_1 c_{s,1}^2
+    (Sec. 4.1, reading R5)."""
+    rho = rho_i.sum(dim=0)
+    w = rho_i / rho
+    u = (w[..., None] * ueq).sum(dim=0)
+    M = torch.tensor(model.M, dtype=DTYPE)
+    n = (rho_i / M[:, None, None, None]).sum(dim=0)
+    p = n * model.M[0] * model.sound2()[0]
+    return rho, u, n, p
+
+
+def cross_relaxation(model, rho_i, rho, n, p):
+    """Inverse cross-relaxation times y_ij = 1/tau_ij at every node, from
+    eq. (relation_tauij_diff_coeff):
+
+      [(rho_i+rho_j)/D_ij + 2 n^2 M_i M_j/(p dt)] y_ij
+          + (1/D_ij) sum_{s != i,j} rho_s y_sj  =  2 rho/(D_ij dt)
+
+    with the index convention of the ternary solution of Sec. 4.1 (reading R3):
+    the unknowns of the pairs (i, j), i < j, that share the larger index j form
+    one dense linear system once the y_js with s > j are known, so the columns
+    are solved for j = N, N-1, ..., 2 with a library solver.
+
+    Returns Y [N, N, nz, ny, nx], symmetric, zero diagonal."""
+    N = model.N
+    D = model.diff
+    M = model.M
+    shape = rho.shape
+    P = rho.numel()
+    r = rho_i.reshape(N, P)
+    R = rho.reshape(P)
+    nn = n.reshape(P)
+    pp = p.reshape(P)
+    Y = [[None] * N for _ in range(N)]
+    zero = torch.zeros(P, dtype=DTYPE)
+    for j in range(N - 1, 0, -1):
+        rows = list(range(j))
+        A = torch.zeros(P, j, j, dtype=DTYPE)
+        b = torch.zeros(P, j, dtype=DTYPE)
+        for ii, i in enumerate(rows):
+            Dij = D[i, j]
+            A_ij = (r[i] + r[j]) / Dij + 2.0 * nn * nn * M[i] * M[j] / pp
+            for kk, s in enumerate(rows):
+                if s == i:
+                    A[:, ii, kk] = A_ij
+                else:
+                    A[:, ii, kk] = r[s] / Dij
+            known = zero
+            for s in range(j + 1, N):
+                known = known + r[s] * Y[j][s]
+            b[:, ii] = 2.0 * R / Dij - known / Dij
+        y = torch.linalg.solve(A, b)
+        for ii, i in enumerate(rows):
+            Y[i][j] = y[:, ii]
+            Y[j][i] = y[:, ii]
+    for i in range(N):
+        Y[i][i] = zero
+    out = torch.stack([torch.stack(row) for row in Y])
+    return out.reshape(N, N, *shape)
+
+
+# -------------------------------------------------------------------- collide
+def equilibria(model, rho_i, ueq, u):
+    """f^(eq) (second-order Hermite form in the mixture velocity u) and
+    f^(0) = [1 + (e - u).(u_i^eq - u)/c_s^2] f^(eq), eq. (feqi0) and the
+    equation after it.  Returns two tensors [N, Q, nz, ny, nx]."""
+    e = model.velocities()
+    w = model.lat.w
+    cs2 = torch.tensor(model.sound2(), dtype=DTYPE)[:, None, None, None, None]
+    eu = torch.einsum("nqc,zyxc->nqzyx", e, u)
+    uu = _dot(u, u)[None, None]
+    feq = w[None, :, None, None, None] * rho_i[:, None] * (
+        1.0 + eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2))
+    du = ueq - u[None]                                     # [N, nz, ny, nx, 3]
+    e_du = torch.einsum("nqc,nzyxc->nqzyx", e, du)
+    u_du = _dot(u[None], du)[:, None]
+    f0 = (1.0 + (e_du - u_du) / cs2) * feq
+    return feq, f0
+
+
+def forcing_term(model, rho_i, u):
+    """Standard forcing term, eq. (CE_forcing_term_discretized):
+    S = omega [ e/c_s^2 + (e e - c_s^2 I).u / c_s^4 ] . F_i,  F_i = rho_i k."""
+    e = model.velocities()
+    w = model.lat.w
+    cs2 = torch.tensor(model.sound2(), dtype=DTYPE)[:, None, None, None, None]
+    k = model.accel().permute(1, 2, 3, 0)                  # [nz, ny, nx, 3]
+    F = rho_i[..., None] * k[None]                         # [N, nz, ny, nx, 3]
+    eF = torch.einsum("nqc,nzyxc->nqzyx", e, F)
+    eu = torch.einsum("nqc,zyxc->nqzyx", e, u)
+    uF = _dot(u[None], F)[:, None]
+    # [e/c2 + (e (e.u) - c2 u)/c2^2] . F
+    S = eF / cs2 + (eu * eF - cs2 * uF) / (cs2 * cs2)
+    return w[None, :, None, None, None] * S
+
+
+def collide(model, f):
+    """f~ = f + Omega^ii + sum_{j!=i} Omega^ij + (1 - dt/(2 tau_i)) S, with
+    Omega^ii = -(f - f^(0))/tau_i                        (eq. BGK_self_collision)
+    Omega^ij = -(1/tau_ij)(rho_j/rho) f^(eq)/c_s^2 (e-u).(u_i^eq - u_j^eq)
+                                                   (eq. Cross_collision_Sirovich)
+    inside eq. (LBE_forcing)."""
+    N = model.N
+    rho_i, ueq = species_moments(model, f)
+    rho, u, n, p = mixture(model, rho_i, ueq)
+    Y = cross_relaxation(model, rho_i, rho, n, p)
+    feq, f0 = equilibria(model, rho_i, ueq, u)
+    S = forcing_term(model, rho_i, u)
+    e = model.velocities()
+    cs2 = model.sound2()
+    tau = model.taus()
+    out = []
+    for i in range(N):
+        omega_self = -(f[i] - f0[i]) / tau[i]
+        e_minus_u = e[i][:, None, None, None, :] - u[None]          # [Q, z, y, x, 3]
+        cross = torch.zeros_like(f[i])
+        for j in range(N):
+            if j == i:
+                continue
+            dv = ueq[i] - ueq[j]                                     # [z, y, x, 3]
+            proj = _dot(e_minus_u, dv[None])
+            cross = cross - Y[i, j][None] * (rho_i[j] / rho)[None] \
+                * feq[i] / cs2[i] * proj
+        out.append(f[i] + omega_self + cross + (1.0 - 0.5 / tau[i]) * S[i])
+    return torch.stack(out)
+
+
+# --------------------------------------------------------------------- stream
+def _shift_source(model, plane, k):
+    """Value of `plane` at O + k for every target O: periodic axes wrap, a
+    source outside a wall axis is solid and contributes nothing."""
+    out = plane
+    for a in range(3):
+        if k[a] == 0:
+            continue
+        dim = AXIS_DIM[a]
+        out = torch.roll(out, shifts=-k[a], dims=dim)
+        if model.walls[a]:
+            n = model.shape_axis(a)
+            idx = torch.arange(n)
+            solid = (idx + k[a] < 0) | (idx + k[a] >= n)
+            shape = [1, 1, 1]
+            shape[dim] = n
+            out = out * (~solid).to(DTYPE).reshape(shape)
+    return out
+
+
+def stream(model, ft):
+    """Pull streaming with the second-order interpolation of eq.
+    (Second_order_spatial_interpolation) (reading R1), generalised to
+    3-D as the product of the 1-D factors, followed by the impermeable-wall
+    scheme of Appendix A (reading R2).
+
+    f^i_alpha(O) = sum_k prod_a lambda_{k_a}(e^i_{alpha,a}) f~^i_alpha(O + k)
+    over k in {-1,0,1}^d with O + k a fluid node.  Species 1 (c = 1) reduces to
+    the exact shift f(O) = f~(O - e).
+
+    Wall scheme (Appendix A, the equations for right, left, upper and bottom
+    walls): at a node O next to a wall on the side sigma (= +1 for the wall at
+    the high end of axis a, -1 for the low end), for every alpha pointing away
+    from that wall (sigma * c_alpha,a < 0) add the parts of f~_alpha(O) and
+    f~_alphabar(O) that would have been streamed into the solid layer:
+        + lambda_{-sigma}(e_alpha,a) f~_alpha(O)
+        + lambda_{-sigma}(e_alphabar,a) f~_alphabar(O).
+    """
+    N, Q = model.N, model.lat.Q
+    e = model.velocities()
+    dim = model.lat.dim
+    offs = [(kx, ky, kz) for kz in ((-1, 0, 1) if dim == 3 else (0,))
+            for ky in (-1, 0, 1) for kx in (-1, 0, 1)]
+    # Lambda_k(e^i_alpha) for every species, direction and source offset.
+    lam = [[[lagrange_weights(float(e[i, al, a])) for a in range(3)]
+            for al in range(Q)] for i in range(N)]
+    out = torch.zeros_like(ft)
+    for k in offs:
+        wk = torch.tensor([[lam[i][al][0][k[0] + 1] * lam[i][al][1][k[1] + 1]
+                            * lam[i][al][2][k[2] + 1] for al in range(Q)]
+                           for i in range(N)], dtype=DTYPE)
+        if not bool((wk != 0).any()):
+            continue
+        out = out + wk[:, :, None, None, None] * _shift_source(model, ft, k)
+    # Appendix A wall terms.
+    for a in range(3):
+        if not model.walls[a]:
+            continue
+        n = model.shape_axis(a)
+        d = AXIS_DIM[a]
+        for sigma in (-1, +1):
+            layer = 0 if sigma < 0 else n - 1
+            wa = torch.zeros(N, Q, dtype=DTYPE)
+            wb = torch.zeros(N, Q, dtype=DTYPE)
+            for i in range(N):
+                for al in range(Q):
+                    if sigma * model.lat.dirs[al][a] >= 0:
+                        continue
+                    ab = model.lat.opp[al]
+                    wa[i, al] = lam[i][al][a][-sigma + 1]
+                    wb[i, al] = lam[i][ab][a][-sigma + 1]
+            here = ft.select(d, layer)                       # [N, Q, ., .]
+            opp = here[:, model.lat.opp]
+            add = wa[:, :, None, None] * here + wb[:, :, None, None] * opp
+            idx = [slice(None)] * 5
+            idx[d] = layer
+            out[tuple(idx)] = out[tuple(idx)] + add
+    return out
+
+
+def step(model, f):
+    """One time step: f(t) -> f(t+1) = stream(collide(f(t)))."""
+    return stream(model, collide(model, f))
+
+
+def run(model, f, steps):
+    for _ in range(steps):
+        f = step(model, f)
+    return f
+
+
+# ----------------------------------------------------------------------- init
+def initial_populations(model, x0):
+    """Initial state from mole fractions x0 [N, nz, ny, nx].
+
+    rho_i = x_i M_i n (Sec. 4.1) with n from default_n0; zero species and
+    mixture velocity; the force-consistent initial velocity
+    u_i0 = u_i^eq - F_i dt/(2 rho_i) = -k/2 replaces u_i^eq in eq. (feqi0)
+    (Sec. 4.2), so with u = 0:  f = [1 + e.u_i0/c_s^2] omega rho_i."""
+    x0 = torch.as_tensor(x0, dtype=DTYPE)
+    M = torch.tensor(model.M, dtype=DTYPE)
+    n = model.default_n0()
+    rho_i = x0 * M[:, None, None, None] * n
+    e = model.velocities()
+    w = model.lat.w
+    cs2 = torch.tensor(model.sound2(), dtype=DTYPE)[:, None, None, None, None]
+    k = model.accel().permute(1, 2, 3, 0)                   # [nz, ny, nx, 3]
+    ui0 = -0.5 * k
+    e_u = torch.einsum("nqc,zyxc->nqzyx", e, ui0)
+    return (1.0 + e_u / cs2) * w[None, :, None, None, None] * rho_i[:, None]
+
+
+# ---------------------------------------------------------------- observables
+def observables(model, f):
+    """Macroscopic fields of a post-stream state f(t) (Sec. 2: moments are
+    taken once streaming and boundary conditions are done):
+      x_i = rho_i / (M_i n)                         (Sec. 3, x_i = rho_i/(n M_i))
+      Theta_i = sum_j rho_i rho_j/(rho tau_ij) (u_i^eq - u_j^eq)
+                                                   (eq. CE_theta_definition)
+      u_i = u_i^eq - dt Theta_i/(2 rho_i)            (eq. CE_EQ83)
+    plus rho_i, u_i^eq, rho, u, n, p and the FP64 total mass of each species."""
+    rho_i, ueq = species_moments(model, f)
+    rho, u, n, p = mixture(model, rho_i, ueq)
+    Y = cross_relaxation(model, rho_i, rho, n, p)
+    M = torch.tensor(model.M, dtype=DTYPE)
+    x = rho_i / (M[:, None, None, None] * n)
+    N = model.N
+    theta = torch.zeros_like(ueq)
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                theta[i] = theta[i] + (rho_i[i] * rho_i[j] / rho * Y[i, j])[..., None] \
+                    * (ueq[i] - ueq[j])
+    safe = torch.where(rho_i == 0, torch.ones_like(rho_i), rho_i)
+    u_real = ueq - 0.5 * theta / safe[..., None]
+    return {
+        "rho_i": rho_i, "ueq": ueq, "rho": rho, "u": u, "n": n, "p": p,
+        "x": x, "tau_inv": Y, "theta": theta, "u_i": u_real,
+        "mass": rho_i.sum(dim=(1, 2, 3)),
+    }
