@@ -1,0 +1,207 @@
+"""Benchmark of the fused EVD multicomponent LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload: the ternary ideal-gas tube with gravity, D2Q9, molar masses
+2:28:44, 1024 x 64 nodes, walls at the x ends, periodic in y, g = 1e-6 along x,
+seeded pair diffusivities, halves of two uniform compositions (synthetic input
+of the paper's Case I structure).  One step is one fused pass (stream with the
+second-order interpolation + impermeable walls + moments + tau solve +
+collision with forcing) over the whole lattice.  The metric is
+MLUPS x species = nodes * species * steps / microseconds, with the state
+resident in HBM before the timed region.
+
+The JSON line also carries
+  roofline:     HBM roofline of the fused step kernel: algorithmic bytes per
+                launch (72 B per species-node for D2Q9: one FP32 read and one
+                FP32 write of 9 populations; 152 B for D3Q19) divided by the
+                average launch time measured with HIP events on the launch
+                stream over the timed region, against 8 TB/s;
+  cpu_baseline: the FP64 oracle timed on this host's CPU cores on a bounded
+                sample of the same workload;
+  accuracy:     max |x_s - x_s(oracle)| of the timed run when the oracle result
+                for that step count is stored, and the FP64 mass drift;
+  hbm_scale:    the same physics on a 16384 x 1024 tube (3.6 GB per step), where
+                the lattice no longer fits the 256 MB last-level cache.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def bytes_per_species_node(lattice):
+    return 2 * 4 * (9 if lattice == "D2Q9" else 19)
+
+
+def workload(name):
+    import lbm_workloads as W
+    if name in ("ternary_gravity_1024x64", "c1"):
+        return W.ternary_gravity()
+    if name in ("ternary_gravity_16384x1024", "c1_hbm"):
+        return W.ternary_gravity(16384, 1024, 500, name="ternary_gravity_16384x1024")
+    if name in ("layer_mixing_3d_256x128x128", "c2"):
+        return W.layer_mixing_3d()
+    if name in ("binary_erf_200x4", "c0"):
+        return W.binary_erf()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_gpu(w, steps, warmup, autotune=False):
+    import numpy as np
+    import torch
+    from paper_2504_07059_amd import lbm
+
+    p = lbm.params_from_workload(w)
+    x0 = w.x0()
+    if autotune:
+        tmp = lbm.LbmMc(p, x0)
+        tmp.autotune(reps=5)
+        tmp.close()
+    sim = lbm.LbmMc(p, x0)
+    m0 = sim.moments(fields=False)["mass"][0].copy()
+    sim.step(warmup)
+    sim.sync()
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    ms = ev0.elapsed_time(ev1)
+    out = sim.moments()
+    drift = float(np.abs(out["mass"][0] / m0 - 1).max())
+    return sim, out, ms, wall, drift
+
+
+def accuracy_vs_golden(w, t=20000):
+    """Paired accuracy gate: a fresh run of the same workload to step t (at the
+    same execution shape) against the stored FP64 oracle result."""
+    import numpy as np
+    from paper_2504_07059_amd import lbm
+    path = os.path.join(ROOT, "tests", "golden", "ternary_gravity.json")
+    if w.name != "ternary_gravity_1024x64" or not os.path.exists(path):
+        return None, None
+    g = json.load(open(path))["checkpoints"][str(t)]
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    m0 = sim.moments(fields=False)["mass"][0].copy()
+    sim.step(t)
+    out = sim.moments()
+    sim.sync()
+    x = sim.field(out, "x").double().cpu().numpy()
+    dx = float(np.abs(x[:, 0] - np.array(g["x"])[:, None, :]).max())
+    drift = float(np.abs(out["mass"][0] / m0 - 1).max())
+    sim.close()
+    return dx, drift
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle, as it stands, on this host's cores: a bounded number of
+    steps of the same workload (initial state included in the setup, not in
+    the timing)."""
+    import torch
+    from oracle import evd
+    from oracle.lattice import DTYPE
+    m = evd.Model(w.lattice, w.nx, w.ny, w.nz, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                  w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+    f = evd.initial_populations(m, torch.tensor(w.x0(), dtype=DTYPE))
+    t0 = time.perf_counter()
+    f = evd.step(m, f)
+    first = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(first, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    f = evd.run(m, f, n)
+    dt = time.perf_counter() - t0
+    value = w.nodes * w.n_species * n / (dt * 1e6)
+    return {"value": value, "unit": "MLUPS x species", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{w.name}: {n} full-lattice FP64 steps in {dt:.1f} s "
+                      f"({torch.get_num_threads()} threads)"}
+
+
+def roofline(w, ms, steps):
+    per_launch = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
+    avg_s = ms * 1e-3 / steps
+    achieved = per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="ternary_gravity_1024x64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-scale companion run")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    w = workload(args.workload)
+    sim, out, ms, wall, drift = time_gpu(w, args.steps, args.warmup, args.autotune)
+    tune = sim.get_tuning()
+    sim.close()
+    acc_dx, acc_drift = accuracy_vs_golden(w)
+    value = w.nodes * w.n_species * args.steps / (ms * 1e3)
+    line = {
+        "metric": "MLUPS x species (fused EVD-LBM step, FP32 state)",
+        "value": value,
+        "unit": "MLUPS x species",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": w.lattice, "nx": w.nx, "ny": w.ny,
+                   "nz": w.nz, "species": w.n_species, "masses": w.masses,
+                   "walls": w.walls, "g": w.g, "tuning": list(tune),
+                   "parallelism": "single GPU"},
+        "roofline": roofline(w, ms, args.steps),
+        "accuracy": {"max_dx_vs_oracle_t20000": acc_dx, "mass_drift_t20000": acc_drift,
+                     "mass_drift_timed_run": drift},
+        "wall_s": wall,
+    }
+    if not args.no_hbm and w.name.startswith("ternary_gravity_1024"):
+        wh = workload("c1_hbm")
+        s2, o2, ms2, wall2, drift2 = time_gpu(wh, wh.steps, 20)
+        t2 = s2.get_tuning()
+        s2.close()
+        line["hbm_scale"] = {
+            "workload": wh.name, "steps": wh.steps,
+            "value": wh.nodes * wh.n_species * wh.steps / (ms2 * 1e3),
+            "unit": "MLUPS x species", "ms_per_step": ms2 / wh.steps,
+            "roofline": roofline(wh, ms2, wh.steps), "mass_drift": drift2,
+            "tuning": list(t2)}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

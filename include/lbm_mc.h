@@ -1,0 +1,248 @@
+/*
+ * lbm_mc -- one GPU (MI355X, gfx950) implementation of the explicit
+ * velocity-difference (EVD) multicomponent lattice Boltzmann method with
+ * forcing of Lourenco, Constantino & Tavares, "Forcing mass transfer approach
+ * in multicomponent miscible mixtures using the lattice Boltzmann method",
+ * Chem. Eng. Sci. 2025 (arXiv 2504.07059).
+ *
+ * The problem the interface encodes is the paper's: N species of given molar
+ * masses (Sec. 4.1, Table 1) with pair Maxwell-Stefan diffusivities D_ij
+ * (Table 2), a viscosity set through tau_1 (Sec. 4 opening), a body force on
+ * each species F_i = rho_i g (eq. MS_equation with k_i = g; Sec. 4.1), an
+ * initial composition x_i(x) with a total mole number n0 (Sec. 4.1), and
+ * impermeable walls (Appendix A) or periodicity on each axis.  The caller
+ * advances the system and observes x_i, rho_i, u and the total mass of every
+ * species (Sec. 4.1: region-averaged mole fractions, total mass).
+ *
+ * Lattice units: dx = dt = 1.  Species must be given in ascending molar mass;
+ * masses are normalised internally so that M_1 = 1 and c_1 = 1 (Sec. 4
+ * opening), and species i then moves with c_i = sqrt(M_1/M_i)
+ * (eq. speed_DLS).
+ *
+ * Memory.  Population buffers are caller-owned device memory (float32); the
+ * library borrows them for the lifetime of a context and never frees them.
+ * Their layout, per lattice, is [species][direction][z][y][x] with the x rows
+ * padded to a pitch of a multiple of 64 floats; lbm_mc_layout() gives the
+ * sizes and offsets.  Several lattices (the batched form) are concatenated in
+ * one buffer.  Populations are stored post-collision: after lbm_mc_init the
+ * "current" buffer holds f~(0), after t steps it holds f~(t).
+ *
+ * Streams.  Every call that launches work does so asynchronously on the HIP
+ * stream given to lbm_mc_init (may be NULL for the null stream).  Calls that
+ * return host values synchronise that stream.
+ *
+ * Errors.  Every entry point returns an lbm_mc_status; on failure
+ * lbm_mc_last_error() gives a thread-local message.  No entry point aborts the
+ * process.  Calls on one context are not thread-safe; separate contexts are
+ * independent.
+ */
+#ifndef LBM_MC_H
+#define LBM_MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_mc_status {
+    LBM_MC_OK = 0,
+    LBM_MC_ERR_INVALID = 1,     /* an argument is invalid (message says which) */
+    LBM_MC_ERR_UNSUPPORTED = 2, /* valid in principle, not provided (walls on two axes, N > 4) */
+    LBM_MC_ERR_HIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
+    LBM_MC_ERR_UNSTABLE = 4,    /* linear stability pre-check of the cross relaxation failed */
+    LBM_MC_ERR_NONFINITE = 5    /* a step produced a non-finite population */
+} lbm_mc_status;
+
+enum { LBM_MC_D2Q9 = 0, LBM_MC_D3Q19 = 1 };
+enum { LBM_MC_PERIODIC = 0, LBM_MC_WALL = 1 };
+
+/* Problem statement of one lattice. */
+typedef struct lbm_mc_params {
+    int32_t lattice;        /* LBM_MC_D2Q9 (the paper's lattice, Sec. 4 opening) or
+                               LBM_MC_D3Q19 (same scheme in 3-D; not in the paper) */
+    int32_t nx, ny, nz;     /* fluid nodes per axis; nz = 1 for D2Q9 */
+    int32_t n_species;      /* 2..4 */
+    int32_t bc[3];          /* per axis x, y, z: LBM_MC_PERIODIC, or LBM_MC_WALL =
+                               impermeable halfway walls beyond both ends of the axis
+                               (Appendix A).  At most one axis may have walls. */
+    double molar_mass[4];   /* molar masses, non-decreasing; any unit (normalised) */
+    double diff[4][4];      /* pair diffusivities D_ij in lattice units, symmetric,
+                               > 0 off the diagonal; the diagonal is ignored */
+    double tau1;            /* relaxation time of species 1, > 1/2; tau_i follows from
+                               a common kinematic viscosity (Sec. 3) */
+    double g[3];            /* specific body force (same for every species): F_i = rho_i g */
+    double n0;              /* initial total mole number n (Sec. 4.1: rho_i = x_i M_i n);
+                               <= 0 selects 1/M_max, i.e. a pure heaviest species would
+                               have rho = 1 (Sec. 4 opening) */
+    int32_t forcing;        /* 0: the standard forcing term (eq. CE_forcing_term_
+                               discretized); other values are rejected */
+    int32_t reserved;       /* must be 0 */
+} lbm_mc_params;
+
+typedef struct lbm_mc_ctx lbm_mc_ctx;
+
+/*
+ * Buffer layout of n_lattices lattices (p[0..n_lattices-1]).  Host only.
+ *   buffer_floats    out: floats each of the two population buffers must hold.
+ *   lattice_offsets  out (may be NULL): n_lattices float offsets of each lattice.
+ *   pitch            out (may be NULL): n_lattices row pitches (floats).
+ *   field_offsets    out (may be NULL): n_lattices node offsets of each lattice in
+ *                    the dense node-field outputs of lbm_mc_moments.
+ * Errors: LBM_MC_ERR_INVALID for NULL or invalid parameters.
+ */
+lbm_mc_status lbm_mc_layout(const lbm_mc_params* p, int32_t n_lattices,
+                            int64_t* buffer_floats, int64_t* lattice_offsets,
+                            int32_t* pitch, int64_t* field_offsets);
+
+/*
+ * Host-only validation of a problem: everything lbm_mc_init checks before it
+ * touches the GPU, including the linear-stability pre-check of the cross
+ * relaxation (a uniform node relaxes species velocity differences with the
+ * matrix I - K, K_ij = -rho_j/(rho tau_ij), K_ii = sum_j rho_j/(rho tau_ij); the
+ * check requires every eigenvalue of K in [0, 2) at sampled initial
+ * compositions and at points between them and the mean composition).
+ *   x0          host float64 initial mole fractions, [lattice][N][nz][ny][nx]
+ *               concatenated over lattices; each node must sum to 1 (1e-9) and be >= 0.
+ *   lambda_max  out (may be NULL): the largest eigenvalue found.
+ * Errors: LBM_MC_ERR_INVALID, LBM_MC_ERR_UNSUPPORTED, LBM_MC_ERR_UNSTABLE.
+ */
+lbm_mc_status lbm_mc_check(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                           double* lambda_max);
+
+/*
+ * Create a context and write the initial state (Sec. 4.1 and 4.2).
+ * rho_i = x_i M_i n0; the species and mixture velocities are zero; the
+ * populations are the equilibrium of eq. (feqi0) with u_i^eq replaced by the
+ * force-consistent u_i0 = -F_i dt/(2 rho_i) (Sec. 4.2), i.e. f(0); these are
+ * collided once so that the current buffer holds f~(0), and f(0) itself is kept
+ * in the other buffer for lbm_mc_moments at t = 0.
+ *   p, n_lattices  problem(s); a batch (n_lattices > 1) must share lattice type
+ *                  and species count.
+ *   x0             host float64, as for lbm_mc_check; copied, not retained.
+ *   f_a, f_b       distinct caller-owned device float buffers of buffer_floats
+ *                  floats each (lbm_mc_layout); borrowed until lbm_mc_destroy.
+ *   hip_stream     the hipStream_t all work is queued on (NULL = null stream).
+ *   out            the new context.
+ * Errors: those of lbm_mc_check, plus LBM_MC_ERR_INVALID for buffers that are
+ * NULL, equal or too small, and LBM_MC_ERR_HIP.  On error *out is NULL.
+ */
+lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                          float* f_a, float* f_b, int64_t buffer_floats, void* hip_stream,
+                          lbm_mc_ctx** out);
+
+/*
+ * Advance every lattice by n_steps time steps (asynchronous).  One step is the
+ * paper's lattice Boltzmann equation with forcing, eq. (LBE_forcing): stream
+ * the post-collision populations with the second-order interpolation of eq.
+ * (Second_order_spatial_interpolation) and the impermeable-wall scheme of
+ * Appendix A, take the moments (eqs. zeroth_order_moment,
+ * first_order_moment_force, Sirovich_mixture_density, Sirovich_mixture_velocity),
+ * solve the cross-relaxation times from eq. (relation_tauij_diff_coeff), and
+ * collide (eqs. BGK_self_collision, Cross_collision_Sirovich, feqi0,
+ * CE_forcing_term_discretized).  The two buffers swap roles every step.
+ * n_steps = 0 is a no-op.  Errors: LBM_MC_ERR_INVALID (NULL ctx, n_steps < 0),
+ * LBM_MC_ERR_HIP.  A non-finite population is reported by the next
+ * lbm_mc_sync or lbm_mc_moments.
+ */
+lbm_mc_status lbm_mc_step(lbm_mc_ctx* ctx, int64_t n_steps);
+
+/* Wait for the context's stream; LBM_MC_ERR_NONFINITE if any step so far
+ * produced a non-finite population (the flag is sticky). */
+lbm_mc_status lbm_mc_sync(lbm_mc_ctx* ctx);
+
+/*
+ * Observables of the post-stream state f(t) at the current step t (Sec. 2:
+ * moments are taken after streaming and boundary conditions).  f(t) is
+ * re-gathered from f~(t-1), which is still in the other buffer (at t = 0 it is
+ * f(0) itself).  Every pointer may be NULL.
+ *   rho   device float [lattice][N][nz][ny][nx]: species densities rho_i.
+ *   x     device float, same layout: mole fractions x_i = rho_i/(M_i n).
+ *   u     device float [lattice][d][nz][ny][nx]: mixture velocity
+ *         u = sum_i w_i u_i^eq with the force-shifted u_i^eq (d = 2 or 3).
+ *   mass      host double [lattice][N]: total mass of each species (FP64 sum).
+ *   momentum  host double [lattice][d]: total sum_x rho u (FP64 sum).
+ * Node-field offsets of each lattice: lbm_mc_layout field_offsets (times N or d).
+ * Requesting mass or momentum synchronises the stream.  Errors:
+ * LBM_MC_ERR_INVALID, LBM_MC_ERR_HIP, LBM_MC_ERR_NONFINITE (as lbm_mc_sync).
+ */
+lbm_mc_status lbm_mc_moments(lbm_mc_ctx* ctx, float* rho, float* x, float* u,
+                             double* mass, double* momentum);
+
+/* Current buffers and step: *cur holds f~(t), *prev holds f~(t-1) (f(0) at t = 0).
+ * Any out pointer may be NULL. */
+lbm_mc_status lbm_mc_state(lbm_mc_ctx* ctx, float** cur, float** prev, int64_t* t);
+
+/*
+ * Checkpoint restore: copy caller buffers (device, buffer_floats each) into the
+ * context's buffers on its stream and set the step counter to t.  cur must hold
+ * f~(t); prev must hold f~(t-1), or f(0) when t = 0, for lbm_mc_moments to be
+ * exact (it may be NULL, then moments are unavailable until the next step).
+ * A run resumed this way is bitwise identical to an uninterrupted one.
+ */
+lbm_mc_status lbm_mc_restore(lbm_mc_ctx* ctx, const float* cur, const float* prev, int64_t t);
+
+/*
+ * One reverse step of the discrete adjoint (single-lattice contexts).  With
+ * Phi = C o S the map f~(t-1) -> f~(t) of lbm_mc_step (S: stream + walls,
+ * C: collide), computes lam_out = (dPhi/df~(t-1))^T lam_in at f_prev = f~(t-1),
+ * and ADDS the parameter gradient g^T (dPhi/dtheta) lam_in into grad.
+ *   f_prev   device float, layout of a population buffer: f~(t-1).
+ *   lam_in   device float, same layout: dL/df~(t).
+ *   lam_out  device float, same layout: dL/df~(t-1) (written; may not alias).
+ *   grad     device double [n_pairs + 3]: dL/dD_ij for the pairs i < j in
+ *            row-major order (in the caller's D units), then dL/dg_x, g_y, g_z.
+ * Uses a context-owned scratch buffer of the size of one population buffer.
+ * Errors: LBM_MC_ERR_INVALID, LBM_MC_ERR_UNSUPPORTED (batched context), HIP.
+ */
+lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* ctx, const float* f_prev, const float* lam_in,
+                                  float* lam_out, double* grad);
+
+/*
+ * Adjoint of the initialisation f~(0) = C(f(0; g)) with respect to the
+ * parameters: ADDS (d f~(0)/d theta)^T lam0 into grad (layout as above).
+ */
+lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* ctx, const float* lam0, double* grad);
+
+/*
+ * Execution shape of the fused step.  block_x: threads along x (32..256, a
+ * multiple of 32); block_y: threads along y in 3-D (1 in 2-D); rows: nodes each
+ * thread marches along the slowest axis; persistent: 0 = one work-group per
+ * tile, >0 = that many resident work-groups looping over the tile list.
+ * Rebuilds the tile list and drops captured graphs.  0 for block_x, block_y or
+ * rows, and -1 for persistent, keep the current value.
+ */
+lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* ctx, int32_t block_x, int32_t block_y,
+                                int32_t rows, int32_t persistent);
+
+/* Query the execution shape in use (any pointer may be NULL). */
+lbm_mc_status lbm_mc_get_tuning(lbm_mc_ctx* ctx, int32_t* block_x, int32_t* block_y,
+                                int32_t* rows, int32_t* persistent);
+
+/*
+ * Autotuner: time `reps` steps of each candidate execution shape (state is not
+ * advanced: candidates read the current buffer and write the other one) and
+ * keep the fastest.  Results are cached per shape class for the process.
+ * best_us (may be NULL) receives the best time per step in microseconds.
+ */
+lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* ctx, int32_t reps, double* best_us);
+
+/*
+ * Batched contexts only: 1 = advance all lattices with one persistent launch per
+ * step (default), 0 = one launch per lattice per step (the single-lattice
+ * kernel applied lattice by lattice, for comparison).
+ */
+lbm_mc_status lbm_mc_set_batched_mode(lbm_mc_ctx* ctx, int32_t one_launch);
+
+/* Release the context's own device tables, scratch and graphs (not f_a, f_b). */
+lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* ctx);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* lbm_mc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_MC_H */

@@ -1,0 +1,223 @@
+// Per-node collision with forcing, in registers (FP32), in deviation form.
+//
+// Input per species (from the gather): P0 (the stored rest population at the
+// node, reference density r* = P0/w_0) and F_a = f_a - w_a r* (a >= 1).  Then
+//   rho_i  = r* + sum_{a>=1} F_a                          eq. (zeroth_order_moment)
+//   rho_i u_i^eq = sum_a e f + F_i/2 = c_i sum_a c_a F_a + rho_i g/2
+//                                                     eq. (first_order_moment_force)
+//            (a species with rho_i below 1e-30 takes u_i^eq = g/2)
+//   rho = sum rho_i, u = sum w_i u_i^eq                   eqs. (Sirovich_mixture_*)
+//   n = sum rho_i/M_i, p = n M_1 c_{s,1}^2                (Sec. 3, Sec. 4.1)
+//   1/tau_ij from eq. (relation_tauij_diff_coeff)         (tau_solve)
+//   f~ = f - (f - f^(0))/tau_i + sum_j Omega^ij + (1 - 1/(2 tau_i)) S
+//        with f^(eq), f^(0) of eq. (feqi0), Omega^ij of eq.
+//        (Cross_collision_Sirovich), S of eq. (CE_forcing_term_discretized);
+// everything is evaluated as a deviation from w_a rho_i (collision conserves
+// rho_i).  The result is stored as P0' = f~_0 and g_a = f~_a - (w_a/w_0) P0'
+// (a >= 1); the rounding error of P0' is handed to the g_a in proportion to
+// w_a, so the stored state keeps rho_i to the precision of the deviations.
+#pragma once
+
+#include "common.hpp"
+#include "lattice.hpp"
+
+namespace lbmmc {
+
+struct CollConst {
+    float c[MAXS], inv_cs2[MAXS], inv_tau[MAXS], fpref[MAXS], invM[MAXS];
+    float K[MAXS][MAXS];
+    float g[3];
+};
+
+__device__ __forceinline__ CollConst coll_const(const LatParams& P) {
+    CollConst C;
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+        C.c[s] = P.c[s]; C.inv_cs2[s] = P.inv_cs2[s]; C.inv_tau[s] = P.inv_tau[s];
+        C.fpref[s] = P.fpref[s]; C.invM[s] = P.invM[s];
+#pragma unroll
+        for (int t = 0; t < MAXS; ++t) C.K[s][t] = P.K[s][t];
+    }
+    C.g[0] = P.g[0]; C.g[1] = P.g[1]; C.g[2] = P.g[2];
+    return C;
+}
+
+// integer direction dotted with a vector (exact adds)
+template <int LAT>
+__device__ __forceinline__ float cdot(int a, float vx, float vy, float vz) {
+    using L = Lat<LAT>;
+    float r = 0.0f;
+    if (L::cx(a) == 1) r += vx; else if (L::cx(a) == -1) r -= vx;
+    if (L::cy(a) == 1) r += vy; else if (L::cy(a) == -1) r -= vy;
+    if (L::DIM == 3) {
+        if (L::cz(a) == 1) r += vz; else if (L::cz(a) == -1) r -= vz;
+    }
+    return r;
+}
+
+// Cross-relaxation solve.  For the pairs (i, j), i < j, that share the larger
+// index j, eq. (relation_tauij_diff_coeff) with the index convention of the
+// ternary solution of Sec. 4.1 reads (D + d rho^T) y = R_j d with
+//   D_i = rho_j/D_ij + 2 n^2 M_i M_j/p,  d_i = 1/D_ij,
+//   R_j = 2 rho - sum_{s>j} rho_s y_js  (known once columns s > j are done),
+// a diagonal matrix plus a rank-one term, whose solution is
+//   y_ij = R_j / (E_ij (1 + q_j)),  E_ij = rho_j + n K_ij,  q_j = sum_{i<j} rho_i/E_ij,
+// with K_ij = 2 M_i M_j D_ij/(M_1 c_{s,1}^2) = 6 M_i M_j D_ij (dt = 1).  All
+// E_ij > 0, so no pivoting is needed.
+template <int NS>
+__device__ __forceinline__ void tau_solve(const float (&rho)[NS], float R, float n,
+                                          const CollConst& C, float (&y)[NS][NS]) {
+#pragma unroll
+    for (int j = NS - 1; j >= 1; --j) {
+        float Rj = 2.0f * R;
+#pragma unroll
+        for (int s = j + 1; s < NS; ++s) Rj -= rho[s] * y[j][s];
+        float iE[NS];
+        float q = 0.0f;
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            iE[i] = 1.0f / (rho[j] + n * C.K[i][j]);
+            q += rho[i] * iE[i];
+        }
+        const float t = Rj / (1.0f + q);
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            y[i][j] = t * iE[i];
+            y[j][i] = y[i][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) y[i][i] = 0.0f;
+}
+
+constexpr float kRhoTiny = 1e-30f;
+
+// Density, force-shifted equilibrium velocity and the deviation-form inputs of
+// every species at one node.
+template <int LAT, int NS>
+__device__ __forceinline__ void node_moments(const float (&P0)[NS],
+                                             const float (&F)[NS][Lat<LAT>::Q],
+                                             const CollConst& C, float (&rho)[NS],
+                                             float (&dlt)[NS], float (&ue)[NS][3]) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const float v = F[s][a];
+            sf += v;
+            if (L::cx(a) == 1) jx += v; else if (L::cx(a) == -1) jx -= v;
+            if (L::cy(a) == 1) jy += v; else if (L::cy(a) == -1) jy -= v;
+            if (L::cz(a) == 1) jz += v; else if (L::cz(a) == -1) jz -= v;
+        }
+        dlt[s] = sf;
+        const float r = fmaf(P0[s], L::inv_w0, sf);
+        rho[s] = r;
+        if (fabsf(r) > kRhoTiny) {
+            const float cr = C.c[s] / r;
+            ue[s][0] = fmaf(jx, cr, 0.5f * C.g[0]);
+            ue[s][1] = fmaf(jy, cr, 0.5f * C.g[1]);
+            ue[s][2] = fmaf(jz, cr, 0.5f * C.g[2]);
+        } else {
+            ue[s][0] = 0.5f * C.g[0];
+            ue[s][1] = 0.5f * C.g[1];
+            ue[s][2] = 0.5f * C.g[2];
+        }
+    }
+}
+
+// Store transform: from the deviations gt_a = f~_a - w_a rho (a >= 1) with
+// rho = P0/w_0 + dlt, produce P0' = f~_0 rounded to float and
+// g_a = f~_a - (w_a/w_0) P0' + w_a (f~_0 - P0')/(1 - w_0).  With
+// T = f~_0 - P0 = w_0 dlt - sum gt and d0 = P0 - P0' (exact: P0' is close to
+// P0), g_a = gt_a + w_a e with e = d0/w_0 + dlt + (d0 + T)/(1 - w_0); all
+// small numbers.  In exact arithmetic P0'/w_0 + sum_{a>=1} g_a = rho.
+template <int LAT>
+__device__ __forceinline__ float store_transform(float P0, float dlt, float sgt, float& e) {
+    using L = Lat<LAT>;
+    const float T = fmaf(L::w(0), dlt, -sgt);
+    const float P0n = P0 + T;
+    const float d0 = P0 - P0n;
+    e = fmaf(d0, L::inv_w0, dlt) + (d0 + T) * L::inv_1mw0;
+    return P0n;
+}
+
+// Collision of one node.  On return P0[s] holds the new stored rest
+// population and F[s][a] (a >= 1) the stored deviations g_a.  Returns false
+// if a result is not finite.
+template <int LAT, int NS>
+__device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
+                                        const CollConst& C) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+    float rho[NS], dlt[NS], ue[NS][3];
+    node_moments<LAT, NS>(P0, F, C, rho, dlt, ue);
+    float R = 0.0f, n = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        R += rho[s];
+        n += rho[s] * C.invM[s];
+    }
+    const float iR = 1.0f / R;
+    float U[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) U[d] = fmaf(rho[s], ue[s][d], U[d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[d] *= iR;
+
+    float y[NS][NS];
+    tau_solve<NS>(rho, R, n, C, y);
+
+    const float uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    bool ok = isfinite(R);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        // friction vector V_i = sum_j (rho_j y_ij / rho)(u_i^eq - u_j^eq)
+        float V[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            if (j == i) continue;
+            const float wij = rho[j] * y[i][j] * iR;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) V[d] = fmaf(wij, ue[i][d] - ue[j][d], V[d]);
+        }
+        const float c = C.c[i], ics = C.inv_cs2[i], itau = C.inv_tau[i], fp = C.fpref[i];
+        const float du0 = ue[i][0] - U[0], du1 = ue[i][1] - U[1], du2 = ue[i][2] - U[2];
+        const float udu = U[0] * du0 + U[1] * du1 + U[2] * du2;
+        const float uV = U[0] * V[0] + U[1] * V[1] + U[2] * V[2];
+        const float F0 = rho[i] * C.g[0], F1 = rho[i] * C.g[1], F2 = rho[i] * C.g[2];
+        const float uF = U[0] * F0 + U[1] * F1 + U[2] * F2;
+        const float b0 = -0.5f * uu * ics;
+        float sgt = 0.0f;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const float wr = L::w(a) * rho[i];
+            const float eu = c * cdot<LAT>(a, U[0], U[1], U[2]);
+            const float edu = c * cdot<LAT>(a, du0, du1, du2);
+            const float eV = c * cdot<LAT>(a, V[0], V[1], V[2]);
+            const float eF = c * cdot<LAT>(a, F0, F1, F2);
+            // f^(eq) - w rho, f^(eq), f^(0) - w rho
+            const float feqd = wr * fmaf(ics * eu, fmaf(0.5f * ics, eu, 1.0f), b0);
+            const float feq = wr + feqd;
+            const float f0d = fmaf(feq * ics, edu - udu, feqd);
+            const float cross = -feq * ics * (eV - uV);
+            const float S = L::w(a) * (ics * (eF - uF) + ics * ics * eu * eF);
+            const float h = fmaf(-L::w(a), dlt[i], F[i][a]);   // f_a - w_a rho
+            const float gt = fmaf(-itau, h - f0d, h) + fmaf(fp, S, cross);
+            F[i][a] = gt;
+            sgt += gt;
+        }
+        float e;
+        P0[i] = store_transform<LAT>(P0[i], dlt[i], sgt, e);
+#pragma unroll
+        for (int a = 1; a < Q; ++a) F[i][a] = fmaf(L::w(a), e, F[i][a]);
+        ok = ok && isfinite(sgt) && isfinite(P0[i]);
+    }
+    return ok;
+}
+
+}  // namespace lbmmc

@@ -1,0 +1,78 @@
+// Data shared by the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmmc {
+
+constexpr int MAXS = 4;
+
+// Per-lattice constants, prepared on the host in double precision and rounded
+// once to float.  One entry per lattice of a (possibly batched) context.
+struct LatParams {
+    int32_t nx, ny, nz, pitch;     // fluid nodes per axis; x-row pitch in floats
+    int64_t base;                  // float offset of this lattice in a population buffer
+    int64_t plane;                 // floats per (species, direction) plane = nz*ny*pitch
+    int64_t field_base;            // node offset of this lattice in dense node fields
+    int32_t wall_axis;             // -1: periodic everywhere; 0/1/2: walls at both ends
+    int32_t n_species;
+    int32_t tile_begin, tile_end;  // this lattice's range in the tile list
+    float lam[MAXS][3];            // (lambda_-1, lambda_0, lambda_+1) at Courant +c_s;
+                                   // the three floats sum to exactly 1
+    float c[MAXS];                 // c_s = sqrt(M_1/M_s)
+    float inv_cs2[MAXS];           // 1/c_{s,s}^2 = 3/c_s^2
+    float inv_tau[MAXS];           // 1/tau_s
+    float fpref[MAXS];             // 1 - 1/(2 tau_s)
+    float invM[MAXS];              // 1/M_s (normalised masses, M_1 = 1)
+    float M[MAXS];                 // normalised masses
+    float K[MAXS][MAXS];           // 2 M_i M_j D_ij / (M_1 c_{s,1}^2) = 6 M_i M_j D_ij
+    float g[3];                    // specific body force
+    float n0;                      // initial total mole number
+    double Kd[MAXS][MAXS];         // the same K in double (adjoint)
+    double dscale[MAXS][MAXS];     // d(D_ij in lattice units)/d(caller D_ij) (1 here)
+};
+
+// One work item of the fused step: a lattice, the origin of a block of
+// cross-section columns, and the range [m0, m1) of layers along the slowest
+// axis that the block marches through.
+struct Tile {
+    int32_t lat;
+    int32_t x0, y0;
+    int32_t m0, m1;
+    int32_t pad[3];
+};
+
+// Launch description handed from the host library to the kernel launchers.
+struct Launch {
+    const float* src;
+    float* dst;
+    const LatParams* lp;
+    const Tile* tiles;
+    int32_t ntiles;
+    int32_t grid;        // work-groups launched (== ntiles when not persistent)
+    int32_t bx, by;      // work-group shape
+    unsigned* flag;      // sticky error flags (bit 0: non-finite)
+    hipStream_t stream;
+};
+
+// Kernel launchers (defined in the .hip translation units).
+hipError_t launch_step(int lattice, int nspecies, const Launch& L);
+hipError_t launch_init(int lattice, int nspecies, const LatParams* lp_dev, int lat,
+                       const LatParams& lp_host, const double* x0_dev, float* f0_out,
+                       float* ft_out, unsigned* flag, hipStream_t s);
+hipError_t launch_moments(int lattice, int nspecies, const Launch& L, int direct, float* rho,
+                          float* x, float* u, double* partial, int nq);
+hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
+                         double* totals, hipStream_t s);
+hipError_t launch_adjoint(int lattice, int nspecies, const Launch& L, const float* lam_in,
+                          float* mu, double* gpart, int ng);
+hipError_t launch_adjoint_stream(int lattice, int nspecies, const Launch& L, const float* mu,
+                                 float* lam_out);
+hipError_t launch_adjoint_init(int lattice, int nspecies, const LatParams* lp_dev,
+                               const LatParams& lp_host, const float* f0, const float* lam0,
+                               double* gpart, int ng, hipStream_t s);
+hipError_t launch_grad_reduce(const double* gpart, int nblocks, int ng, double* grad,
+                              hipStream_t s);
+
+}  // namespace lbmmc

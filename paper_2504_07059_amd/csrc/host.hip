@@ -1,0 +1,845 @@
+// Host side of the C ABI declared in include/lbm_mc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lbm_mc.h"
+#include "common.hpp"
+
+using namespace lbmmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_mc_status fail(lbm_mc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHECK(expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LBM_MC_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+constexpr int kPitchAlign = 32;   // floats: 128-byte rows
+constexpr int kBaseAlign = 64;    // floats: 256-byte lattice bases
+
+int q_of(int lattice) { return lattice == LBM_MC_D2Q9 ? 9 : 19; }
+int dim_of(int lattice) { return lattice == LBM_MC_D2Q9 ? 2 : 3; }
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------ validation
+lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
+    if (!p) return fail(LBM_MC_ERR_INVALID, "params is NULL");
+    if (L < 1) return fail(LBM_MC_ERR_INVALID, "n_lattices must be >= 1 (got %d)", L);
+    for (int l = 0; l < L; ++l) {
+        const lbm_mc_params& q = p[l];
+        if (q.lattice != LBM_MC_D2Q9 && q.lattice != LBM_MC_D3Q19)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: unknown lattice type %d", l, q.lattice);
+        if (q.lattice != p[0].lattice || q.n_species != p[0].n_species)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: a batch must share lattice type and species count", l);
+        if (q.n_species < 2 || q.n_species > 4)
+            return fail(q.n_species > 4 ? LBM_MC_ERR_UNSUPPORTED : LBM_MC_ERR_INVALID,
+                        "lattice %d: n_species must be 2..4 (got %d)", l, q.n_species);
+        if (q.nx < 1 || q.ny < 1 || q.nz < 1)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: nx, ny, nz must be >= 1", l);
+        if (q.lattice == LBM_MC_D2Q9 && q.nz != 1)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: D2Q9 needs nz = 1", l);
+        if ((int64_t)q.nx * q.ny * q.nz > (int64_t)1 << 31)
+            return fail(LBM_MC_ERR_UNSUPPORTED, "lattice %d: more than 2^31 nodes", l);
+        int walls = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (q.bc[a] != LBM_MC_PERIODIC && q.bc[a] != LBM_MC_WALL)
+                return fail(LBM_MC_ERR_INVALID, "lattice %d: bc[%d] must be PERIODIC or WALL", l, a);
+            if (q.bc[a] == LBM_MC_WALL) {
+                ++walls;
+                const int n = a == 0 ? q.nx : (a == 1 ? q.ny : q.nz);
+                if (n < 2)
+                    return fail(LBM_MC_ERR_INVALID, "lattice %d: a wall axis needs >= 2 nodes", l);
+            }
+        }
+        if (q.lattice == LBM_MC_D2Q9 && q.bc[2] == LBM_MC_WALL)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: no z walls in 2-D", l);
+        if (walls > 1)
+            return fail(LBM_MC_ERR_UNSUPPORTED,
+                        "lattice %d: walls on more than one axis (corners) are not supported", l);
+        const int N = q.n_species;
+        for (int i = 0; i < N; ++i) {
+            if (!(q.molar_mass[i] > 0.0) || !std::isfinite(q.molar_mass[i]))
+                return fail(LBM_MC_ERR_INVALID, "lattice %d: molar_mass[%d] must be > 0", l, i);
+            if (i > 0 && q.molar_mass[i] < q.molar_mass[i - 1])
+                return fail(LBM_MC_ERR_INVALID,
+                            "lattice %d: species must be ordered by ascending molar mass", l);
+            for (int j = 0; j < N; ++j) {
+                if (i == j) continue;
+                const double d = q.diff[i][j], e = q.diff[j][i];
+                if (!(d > 0.0) || !std::isfinite(d))
+                    return fail(LBM_MC_ERR_INVALID, "lattice %d: diff[%d][%d] must be > 0", l, i, j);
+                if (std::fabs(d - e) > 1e-12 * std::fabs(d))
+                    return fail(LBM_MC_ERR_INVALID, "lattice %d: diff must be symmetric", l);
+            }
+        }
+        if (!(q.tau1 > 0.5) || !std::isfinite(q.tau1))
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: tau1 must be > 1/2 (got %g)", l, q.tau1);
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(q.g[a])) return fail(LBM_MC_ERR_INVALID, "lattice %d: g not finite", l);
+        if (q.lattice == LBM_MC_D2Q9 && q.g[2] != 0.0)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: g[2] must be 0 in 2-D", l);
+        if (!std::isfinite(q.n0)) return fail(LBM_MC_ERR_INVALID, "lattice %d: n0 not finite", l);
+        if (q.forcing != 0)
+            return fail(LBM_MC_ERR_UNSUPPORTED, "lattice %d: only forcing = 0 is provided", l);
+        if (q.reserved != 0) return fail(LBM_MC_ERR_INVALID, "lattice %d: reserved must be 0", l);
+    }
+    return LBM_MC_OK;
+}
+
+// Normalised problem of one lattice in double precision.
+struct Norm {
+    int N;
+    double M[MAXS], c[MAXS], cs2[MAXS], tau[MAXS], D[MAXS][MAXS], n0;
+};
+
+Norm normalise(const lbm_mc_params& q) {
+    Norm r{};
+    r.N = q.n_species;
+    double mmax = 0.0;
+    for (int i = 0; i < r.N; ++i) {
+        r.M[i] = q.molar_mass[i] / q.molar_mass[0];   // M_1 = 1 (Sec. 4 opening)
+        r.c[i] = std::sqrt(1.0 / r.M[i]);             // eq. (speed_DLS)
+        r.cs2[i] = r.c[i] * r.c[i] / 3.0;
+        r.tau[i] = 0.5 + (q.tau1 - 0.5) * r.M[i];     // common nu (Sec. 3)
+        mmax = std::max(mmax, r.M[i]);
+        for (int j = 0; j < r.N; ++j) r.D[i][j] = q.diff[i][j];
+    }
+    r.n0 = q.n0 > 0.0 ? q.n0 : 1.0 / mmax;
+    return r;
+}
+
+// 1/tau_ij at one node (double), the closed form of the kernel's tau_solve.
+void inv_taus(const Norm& nm, const double* rho, double y[MAXS][MAXS]) {
+    const int N = nm.N;
+    double R = 0.0, n = 0.0;
+    for (int i = 0; i < N; ++i) {
+        R += rho[i];
+        n += rho[i] / nm.M[i];
+    }
+    for (int i = 0; i < MAXS; ++i)
+        for (int j = 0; j < MAXS; ++j) y[i][j] = 0.0;
+    for (int j = N - 1; j >= 1; --j) {
+        double Rj = 2.0 * R;
+        for (int s = j + 1; s < N; ++s) Rj -= rho[s] * y[j][s];
+        double E[MAXS], q = 0.0;
+        for (int i = 0; i < j; ++i) {
+            E[i] = rho[j] + n * 6.0 * nm.M[i] * nm.M[j] * nm.D[i][j];
+            q += rho[i] / E[i];
+        }
+        for (int i = 0; i < j; ++i) y[i][j] = y[j][i] = Rj / (E[i] * (1.0 + q));
+    }
+}
+
+// Eigenvalues of a small symmetric matrix (cyclic Jacobi).
+void sym_eig(int n, double A[MAXS][MAXS], double* ev) {
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += A[i][j] * A[i][j];
+        if (off < 1e-30) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                if (std::fabs(A[p][q]) < 1e-300) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i) ev[i] = A[i][i];
+}
+
+// Eigenvalue range of the velocity-difference relaxation matrix K at a
+// uniform node of composition x (rho_i = x_i M_i n0).  K is similar to the
+// symmetric S_ij = -sqrt(rho_i rho_j) y_ij / rho (i != j), S_ii = K_ii.
+void k_eig_range(const Norm& nm, const double* x, double& lo, double& hi) {
+    const int N = nm.N;
+    double rho[MAXS], R = 0.0;
+    for (int i = 0; i < N; ++i) {
+        rho[i] = x[i] * nm.M[i] * nm.n0;
+        R += rho[i];
+    }
+    double y[MAXS][MAXS];
+    inv_taus(nm, rho, y);
+    double S[MAXS][MAXS] = {};
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < N; ++j) {
+            if (i == j) continue;
+            S[i][i] += rho[j] * y[i][j] / R;
+            S[i][j] = -std::sqrt(rho[i] * rho[j]) * y[i][j] / R;
+        }
+    }
+    double ev[MAXS];
+    sym_eig(N, S, ev);
+    lo = ev[0];
+    hi = ev[0];
+    for (int i = 1; i < N; ++i) {
+        lo = std::min(lo, ev[i]);
+        hi = std::max(hi, ev[i]);
+    }
+}
+
+lbm_mc_status validate_x0_and_stability(const lbm_mc_params* p, int32_t L, const double* x0,
+                                        double* lam_out) {
+    if (!x0) return fail(LBM_MC_ERR_INVALID, "x0 is NULL");
+    double worst = 0.0;
+    int64_t off = 0;
+    for (int l = 0; l < L; ++l) {
+        const lbm_mc_params& q = p[l];
+        const int N = q.n_species;
+        const int64_t nodes = (int64_t)q.nx * q.ny * q.nz;
+        const double* xl = x0 + off;
+        off += nodes * N;
+        double mean[MAXS] = {};
+        for (int64_t k = 0; k < nodes; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) {
+                const double v = xl[i * nodes + k];
+                if (!(v >= 0.0) || !std::isfinite(v))
+                    return fail(LBM_MC_ERR_INVALID,
+                                "lattice %d: x0 must be finite and >= 0 (node %lld species %d)", l,
+                                (long long)k, i);
+                s += v;
+                mean[i] += v;
+            }
+            if (std::fabs(s - 1.0) > 1e-9)
+                return fail(LBM_MC_ERR_INVALID, "lattice %d: x0 does not sum to 1 at node %lld", l,
+                            (long long)k);
+        }
+        for (int i = 0; i < N; ++i) mean[i] /= (double)nodes;
+        const Norm nm = normalise(q);
+        // distinct compositions among up to 2048 evenly spaced nodes
+        std::set<std::vector<long long>> seen;
+        std::vector<std::vector<double>> comps;
+        const int64_t stride = std::max<int64_t>(1, nodes / 2048);
+        for (int64_t k = 0; k < nodes; k += stride) {
+            std::vector<long long> key(N);
+            std::vector<double> xs(N);
+            for (int i = 0; i < N; ++i) {
+                xs[i] = xl[i * nodes + k];
+                key[i] = std::llround(xs[i] * 1e9);
+            }
+            if (seen.insert(key).second) comps.push_back(xs);
+        }
+        comps.push_back(std::vector<double>(mean, mean + N));
+        const double ts[4] = {0.0, 0.25, 0.5, 0.75};
+        for (const auto& xs : comps) {
+            for (double t : ts) {
+                double xt[MAXS];
+                for (int i = 0; i < N; ++i) xt[i] = (1.0 - t) * xs[i] + t * mean[i];
+                double lo, hi;
+                k_eig_range(nm, xt, lo, hi);
+                worst = std::max(worst, hi);
+                if (hi >= 2.0 || lo < -1e-12) {
+                    if (lam_out) *lam_out = hi;
+                    return fail(LBM_MC_ERR_UNSTABLE,
+                                "lattice %d: cross relaxation is linearly unstable (eigenvalues of K "
+                                "in [%g, %g], need [0, 2)); reduce D_ij or the densities",
+                                l, lo, hi);
+                }
+            }
+        }
+    }
+    if (lam_out) *lam_out = worst;
+    return LBM_MC_OK;
+}
+
+// Interpolation weights of Courant number c rounded to floats whose sum is
+// exactly 1: lambda_-1 and lambda_+1 are rounded to the 2^-24 grid, so that
+// 1 - lambda_-1 - lambda_+1 is exactly representable.
+void exact_triple(double c, float out[3]) {
+    const double lm = c * (1.0 + c) / 2.0, lp = -c * (1.0 - c) / 2.0;
+    const double grid = std::ldexp(1.0, -24);
+    const double a = std::nearbyint(lm / grid) * grid, b = std::nearbyint(lp / grid) * grid;
+    out[0] = (float)a;
+    out[2] = (float)b;
+    out[1] = (float)(1.0 - a - b);
+}
+
+struct Layout {
+    std::vector<int64_t> base, field;
+    std::vector<int32_t> pitch;
+    int64_t total = 0;
+};
+
+Layout make_layout(const lbm_mc_params* p, int32_t L) {
+    Layout lo;
+    int64_t fb = 0;
+    for (int l = 0; l < L; ++l) {
+        const auto& q = p[l];
+        const int pitch = (int)round_up(q.nx, kPitchAlign);
+        lo.pitch.push_back(pitch);
+        lo.base.push_back(lo.total);
+        lo.field.push_back(fb);
+        const int64_t plane = (int64_t)q.nz * q.ny * pitch;
+        lo.total = round_up(lo.total + plane * q.n_species * q_of(q.lattice), kBaseAlign);
+        fb += (int64_t)q.nx * q.ny * q.nz;
+    }
+    return lo;
+}
+
+struct Tuning {
+    int bx = 256, by = 1, rows = 32, persistent = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int>, Tuning> g_tune_cache;
+
+}  // namespace
+
+struct lbm_mc_ctx {
+    int lattice = 0, N = 0, L = 0, Q = 9, DIM = 2;
+    std::vector<lbm_mc_params> params;
+    std::vector<LatParams> hlp;
+    LatParams* dlp = nullptr;
+    Layout layout;
+    float* bufA = nullptr;
+    float* bufB = nullptr;
+    float* cur = nullptr;
+    float* prev = nullptr;
+    bool prev_valid = false;
+    int64_t t = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    unsigned* dflag = nullptr;
+    // tiles
+    Tuning tune;
+    std::vector<Tile> htiles;
+    Tile* dtiles = nullptr;
+    size_t dtiles_cap = 0;
+    double* dpartial = nullptr;
+    size_t dpartial_cap = 0;
+    double* dtotals = nullptr;
+    int one_launch = 1;
+    int cus = 256;
+    // captured step graphs (index: cur == bufA)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gsteps = 32;
+    // adjoint scratch
+    float* dmu = nullptr;
+    double* dgpart = nullptr;
+    size_t dgpart_cap = 0;
+    float* df0scratch = nullptr;
+};
+
+namespace {
+
+void drop_graphs(lbm_mc_ctx* c) {
+    for (auto& g : c->gexec) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+lbm_mc_status build_tiles(lbm_mc_ctx* c) {
+    c->htiles.clear();
+    const Tuning& T = c->tune;
+    for (int l = 0; l < c->L; ++l) {
+        const auto& q = c->params[l];
+        const int nm = c->DIM == 2 ? q.ny : q.nz;
+        const int nxb = (q.nx + T.bx - 1) / T.bx;
+        const int nyb = c->DIM == 3 ? (q.ny + T.by - 1) / T.by : 1;
+        const int nmc = (nm + T.rows - 1) / T.rows;
+        c->hlp[l].tile_begin = (int)c->htiles.size();
+        for (int xb = 0; xb < nxb; ++xb)
+            for (int yb = 0; yb < nyb; ++yb)
+                for (int mc = 0; mc < nmc; ++mc) {
+                    Tile t{};
+                    t.lat = l;
+                    t.x0 = xb * T.bx;
+                    t.y0 = yb * T.by;
+                    t.m0 = mc * T.rows;
+                    t.m1 = std::min(nm, (mc + 1) * T.rows);
+                    c->htiles.push_back(t);
+                }
+        c->hlp[l].tile_end = (int)c->htiles.size();
+    }
+    const size_t nt = c->htiles.size();
+    if (nt > c->dtiles_cap) {
+        if (c->dtiles) hipFree(c->dtiles);
+        c->dtiles = nullptr;
+        HIPCHECK(hipMalloc(&c->dtiles, nt * sizeof(Tile)));
+        c->dtiles_cap = nt;
+    }
+    const size_t np = nt * (size_t)(c->N + 3);
+    if (np > c->dpartial_cap) {
+        if (c->dpartial) hipFree(c->dpartial);
+        c->dpartial = nullptr;
+        HIPCHECK(hipMalloc(&c->dpartial, np * sizeof(double)));
+        c->dpartial_cap = np;
+    }
+    HIPCHECK(hipMemcpyAsync(c->dtiles, c->htiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice,
+                            c->stream));
+    HIPCHECK(hipMemcpyAsync(c->dlp, c->hlp.data(), c->hlp.size() * sizeof(LatParams),
+                            hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    return LBM_MC_OK;
+}
+
+Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
+    Launch L{};
+    L.src = src;
+    L.dst = dst;
+    L.lp = c->dlp;
+    L.tiles = c->dtiles;
+    L.ntiles = (int)c->htiles.size();
+    L.grid = c->tune.persistent > 0 ? std::min(L.ntiles, c->tune.persistent) : L.ntiles;
+    L.bx = c->tune.bx;
+    L.by = c->tune.by;
+    L.flag = c->dflag;
+    L.stream = s;
+    return L;
+}
+
+// One step from src to dst (all lattices).
+lbm_mc_status launch_one(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
+    if (c->L > 1 && !c->one_launch) {
+        for (int l = 0; l < c->L; ++l) {
+            Launch L = make_launch(c, src, dst, s);
+            L.tiles = c->dtiles + c->hlp[l].tile_begin;
+            L.ntiles = c->hlp[l].tile_end - c->hlp[l].tile_begin;
+            L.grid = L.ntiles;
+            HIPCHECK(launch_step(c->lattice, c->N, L));
+        }
+        return LBM_MC_OK;
+    }
+    HIPCHECK(launch_step(c->lattice, c->N, make_launch(c, src, dst, s)));
+    return LBM_MC_OK;
+}
+
+lbm_mc_status get_graph(lbm_mc_ctx* c, hipGraphExec_t* out) {
+    const int key = c->cur == c->bufA ? 0 : 1;
+    if (!c->gexec[key]) {
+        HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        float* src = c->cur;
+        float* dst = c->prev;
+        lbm_mc_status st = LBM_MC_OK;
+        for (int i = 0; i < c->gsteps && st == LBM_MC_OK; ++i) {
+            st = launch_one(c, src, dst, c->cap);
+            std::swap(src, dst);
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap, &g);
+        if (st != LBM_MC_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(LBM_MC_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    *out = c->gexec[key];
+    return LBM_MC_OK;
+}
+
+lbm_mc_status check_flag(lbm_mc_ctx* c) {
+    unsigned f = 0;
+    HIPCHECK(hipMemcpyAsync(&f, c->dflag, sizeof f, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    if (f & 1u)
+        return fail(LBM_MC_ERR_NONFINITE,
+                    "a step produced a non-finite population (unstable parameters or input)");
+    return LBM_MC_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* lbm_mc_last_error(void) { return g_err.c_str(); }
+
+lbm_mc_status lbm_mc_layout(const lbm_mc_params* p, int32_t n_lattices, int64_t* buffer_floats,
+                            int64_t* lattice_offsets, int32_t* pitch, int64_t* field_offsets) {
+    lbm_mc_status st = validate_params(p, n_lattices);
+    if (st != LBM_MC_OK) return st;
+    if (!buffer_floats) return fail(LBM_MC_ERR_INVALID, "buffer_floats is NULL");
+    Layout lo = make_layout(p, n_lattices);
+    *buffer_floats = lo.total;
+    for (int l = 0; l < n_lattices; ++l) {
+        if (lattice_offsets) lattice_offsets[l] = lo.base[l];
+        if (pitch) pitch[l] = lo.pitch[l];
+        if (field_offsets) field_offsets[l] = lo.field[l];
+    }
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_check(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                           double* lambda_max) {
+    lbm_mc_status st = validate_params(p, n_lattices);
+    if (st != LBM_MC_OK) return st;
+    return validate_x0_and_stability(p, n_lattices, x0, lambda_max);
+}
+
+lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const double* x0, float* f_a,
+                          float* f_b, int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out) {
+    if (!out) return fail(LBM_MC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    lbm_mc_status st = lbm_mc_check(p, n_lattices, x0, nullptr);
+    if (st != LBM_MC_OK) return st;
+    if (!f_a || !f_b) return fail(LBM_MC_ERR_INVALID, "population buffers must not be NULL");
+    if (f_a == f_b) return fail(LBM_MC_ERR_INVALID, "f_a and f_b must be distinct buffers");
+    Layout lo = make_layout(p, n_lattices);
+    if (buffer_floats < lo.total)
+        return fail(LBM_MC_ERR_INVALID, "buffers hold %lld floats, %lld needed",
+                    (long long)buffer_floats, (long long)lo.total);
+    const uintptr_t a0 = (uintptr_t)f_a, a1 = (uintptr_t)f_b;
+    const uintptr_t bytes = (uintptr_t)lo.total * sizeof(float);
+    if (a0 < a1 + bytes && a1 < a0 + bytes)
+        return fail(LBM_MC_ERR_INVALID, "f_a and f_b overlap");
+    if ((a0 | a1) % 16)
+        return fail(LBM_MC_ERR_INVALID, "population buffers must be 16-byte aligned");
+
+    auto* c = new lbm_mc_ctx();
+    c->lattice = p[0].lattice;
+    c->N = p[0].n_species;
+    c->L = n_lattices;
+    c->Q = q_of(c->lattice);
+    c->DIM = dim_of(c->lattice);
+    c->params.assign(p, p + n_lattices);
+    c->layout = lo;
+    c->bufA = f_a;
+    c->bufB = f_b;
+    c->cur = f_a;
+    c->prev = f_b;
+    c->stream = (hipStream_t)hip_stream;
+    auto bail = [&](lbm_mc_status s) {
+        std::string keep = g_err;
+        lbm_mc_destroy(c);
+        g_err = keep;
+        return s;
+    };
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "no HIP device"));
+    hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(LBM_MC_ERR_HIP, "stream create failed"));
+
+    // per-lattice constants
+    c->hlp.resize(n_lattices);
+    for (int l = 0; l < n_lattices; ++l) {
+        const auto& q = p[l];
+        const Norm nm = normalise(q);
+        LatParams& P = c->hlp[l];
+        memset(&P, 0, sizeof P);
+        P.nx = q.nx; P.ny = q.ny; P.nz = q.nz;
+        P.pitch = lo.pitch[l];
+        P.base = lo.base[l];
+        P.plane = (int64_t)q.nz * q.ny * lo.pitch[l];
+        P.field_base = lo.field[l];
+        P.wall_axis = -1;
+        for (int a = 0; a < 3; ++a)
+            if (q.bc[a] == LBM_MC_WALL) P.wall_axis = a;
+        P.n_species = q.n_species;
+        for (int i = 0; i < MAXS; ++i) {
+            if (i < nm.N) {
+                exact_triple(nm.c[i], P.lam[i]);
+                P.c[i] = (float)nm.c[i];
+                P.inv_cs2[i] = (float)(1.0 / nm.cs2[i]);
+                P.inv_tau[i] = (float)(1.0 / nm.tau[i]);
+                P.fpref[i] = (float)(1.0 - 0.5 / nm.tau[i]);
+                P.invM[i] = (float)(1.0 / nm.M[i]);
+                P.M[i] = (float)nm.M[i];
+                for (int j = 0; j < nm.N; ++j) {
+                    const double k = i == j ? 0.0 : 6.0 * nm.M[i] * nm.M[j] * nm.D[i][j];
+                    P.K[i][j] = (float)k;
+                    P.Kd[i][j] = k;
+                    P.dscale[i][j] = 1.0;
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) P.g[a] = (float)q.g[a];
+        P.n0 = (float)nm.n0;
+    }
+    if (hipMalloc(&c->dlp, n_lattices * sizeof(LatParams)) != hipSuccess ||
+        hipMalloc(&c->dflag, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c->dtotals, (size_t)n_lattices * (c->N + 3) * sizeof(double)) != hipSuccess)
+        return bail(fail(LBM_MC_ERR_HIP, "device allocation failed"));
+    if (hipMemsetAsync(c->dflag, 0, sizeof(unsigned), c->stream) != hipSuccess)
+        return bail(fail(LBM_MC_ERR_HIP, "memset failed"));
+
+    // default execution shape, or a cached autotuned one
+    Tuning t;
+    if (c->DIM == 3) {
+        t.bx = 64; t.by = 4; t.rows = 16;
+    } else {
+        t.bx = p[0].nx >= 256 ? 256 : (p[0].nx >= 128 ? 128 : 64);
+        t.rows = 16;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find({c->lattice, c->N, p[0].nx, p[0].ny, p[0].nz, n_lattices});
+        if (it != g_tune_cache.end()) t = it->second;
+    }
+    c->tune = t;
+    st = build_tiles(c);
+    if (st != LBM_MC_OK) return bail(st);
+
+    // initial state: f(0) into f_b, f~(0) into f_a
+    double* dx0 = nullptr;
+    int64_t nx0 = 0;
+    for (int l = 0; l < n_lattices; ++l) nx0 += (int64_t)p[l].nx * p[l].ny * p[l].nz * c->N;
+    if (hipMalloc(&dx0, nx0 * sizeof(double)) != hipSuccess)
+        return bail(fail(LBM_MC_ERR_HIP, "x0 staging allocation failed"));
+    hipError_t e = hipMemcpyAsync(dx0, x0, nx0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    for (int l = 0; l < n_lattices && e == hipSuccess; ++l)
+        e = launch_init(c->lattice, c->N, c->dlp, l, c->hlp[l], dx0, c->prev, c->cur, c->dflag,
+                        c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipFree(dx0);
+    if (e != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "init: %s", hipGetErrorString(e)));
+    c->prev_valid = true;
+    c->t = 0;
+    st = check_flag(c);
+    if (st != LBM_MC_OK) return bail(st);
+    *out = c;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_step(lbm_mc_ctx* c, int64_t n) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(LBM_MC_ERR_INVALID, "n_steps must be >= 0");
+    while (n > 0) {
+        if (n >= c->gsteps) {
+            hipGraphExec_t g;
+            lbm_mc_status st = get_graph(c, &g);
+            if (st != LBM_MC_OK) return st;
+            HIPCHECK(hipGraphLaunch(g, c->stream));
+            n -= c->gsteps;
+            c->t += c->gsteps;   // gsteps is even: cur/prev are back in place
+        } else {
+            lbm_mc_status st = launch_one(c, c->cur, c->prev, c->stream);
+            if (st != LBM_MC_OK) return st;
+            std::swap(c->cur, c->prev);
+            c->t += 1;
+            n -= 1;
+        }
+        c->prev_valid = true;
+    }
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_sync(lbm_mc_ctx* c) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    return check_flag(c);
+}
+
+lbm_mc_status lbm_mc_moments(lbm_mc_ctx* c, float* rho, float* x, float* u, double* mass,
+                             double* momentum) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (!c->prev_valid)
+        return fail(LBM_MC_ERR_INVALID, "moments need f~(t-1): restore it or take one step");
+    const int nq = c->N + 3;
+    Launch L = make_launch(c, c->prev, nullptr, c->stream);
+    if (c->tune.bx * c->tune.by % 64) return fail(LBM_MC_ERR_INVALID, "block size must be a multiple of 64");
+    HIPCHECK(launch_moments(c->lattice, c->N, L, c->t == 0 ? 1 : 0, rho, x, u, c->dpartial, nq));
+    if (mass || momentum) {
+        HIPCHECK(launch_reduce(c->dlp, c->L, c->dpartial, nq, c->dtotals, c->stream));
+        std::vector<double> h((size_t)c->L * nq);
+        HIPCHECK(hipMemcpyAsync(h.data(), c->dtotals, h.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        for (int l = 0; l < c->L; ++l) {
+            if (mass)
+                for (int s = 0; s < c->N; ++s) mass[l * c->N + s] = h[(size_t)l * nq + s];
+            if (momentum)
+                for (int d = 0; d < c->DIM; ++d) momentum[l * c->DIM + d] = h[(size_t)l * nq + c->N + d];
+        }
+        return check_flag(c);
+    }
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_state(lbm_mc_ctx* c, float** cur, float** prev, int64_t* t) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (cur) *cur = c->cur;
+    if (prev) *prev = c->prev;
+    if (t) *t = c->t;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_restore(lbm_mc_ctx* c, const float* cur, const float* prev, int64_t t) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (!cur) return fail(LBM_MC_ERR_INVALID, "cur is NULL");
+    if (t < 0) return fail(LBM_MC_ERR_INVALID, "t must be >= 0");
+    const size_t bytes = (size_t)c->layout.total * sizeof(float);
+    if (cur != c->cur) HIPCHECK(hipMemcpyAsync(c->cur, cur, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (prev && prev != c->prev)
+        HIPCHECK(hipMemcpyAsync(c->prev, prev, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->prev_valid = prev != nullptr;
+    c->t = t;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* c, int32_t bx, int32_t by, int32_t rows,
+                                int32_t persistent) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    Tuning t = c->tune;
+    if (bx) t.bx = bx;
+    if (by) t.by = by;
+    if (rows) t.rows = rows;
+    if (persistent >= 0) t.persistent = persistent;
+    if (t.bx < 32 || t.bx > 256 || t.bx % 32) return fail(LBM_MC_ERR_INVALID, "block_x must be 32..256, multiple of 32");
+    if (c->DIM == 2 && t.by != 1) return fail(LBM_MC_ERR_INVALID, "block_y must be 1 in 2-D");
+    if (t.by < 1 || t.bx * t.by > 256 || (t.bx * t.by) % 64)
+        return fail(LBM_MC_ERR_INVALID, "block_x*block_y must be 64, 128, 192 or 256");
+    if (t.rows < 1) return fail(LBM_MC_ERR_INVALID, "rows must be >= 1");
+    c->tune = t;
+    return build_tiles(c);
+}
+
+lbm_mc_status lbm_mc_get_tuning(lbm_mc_ctx* c, int32_t* bx, int32_t* by, int32_t* rows,
+                                int32_t* persistent) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (bx) *bx = c->tune.bx;
+    if (by) *by = c->tune.by;
+    if (rows) *rows = c->tune.rows;
+    if (persistent) *persistent = c->tune.persistent;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (reps < 1) return fail(LBM_MC_ERR_INVALID, "reps must be >= 1");
+    std::vector<Tuning> cands;
+    const int nm = c->DIM == 2 ? c->params[0].ny : c->params[0].nz;
+    const int rowsv[] = {4, 8, 16, 32, 64, 128};
+    const int pers[] = {0, 1};
+    if (c->DIM == 2) {
+        for (int bx : {64, 128, 256})
+            for (int r : rowsv)
+                for (int ps : pers) {
+                    if (r > 2 * nm && r != 4) continue;
+                    Tuning t;
+                    t.bx = bx; t.by = 1; t.rows = r;
+                    t.persistent = ps ? c->cus * (1024 / bx) : 0;
+                    cands.push_back(t);
+                }
+    } else {
+        for (int bx : {32, 64, 128})
+            for (int by : {1, 2, 4, 8})
+                for (int r : {8, 16, 32, 64}) {
+                    if (bx * by < 64 || bx * by > 256) continue;
+                    if (r > 2 * nm && r != 8) continue;
+                    Tuning t;
+                    t.bx = bx; t.by = by; t.rows = r; t.persistent = 0;
+                    cands.push_back(t);
+                }
+    }
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    double best = 1e300;
+    Tuning bestt = c->tune;
+    for (const Tuning& t : cands) {
+        c->tune = t;
+        lbm_mc_status st = build_tiles(c);
+        if (st != LBM_MC_OK) return st;
+        for (int i = 0; i < 2; ++i) {
+            st = launch_one(c, c->cur, c->prev, c->stream);
+            if (st != LBM_MC_OK) return st;
+        }
+        HIPCHECK(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < reps; ++i) {
+            st = launch_one(c, c->cur, c->prev, c->stream);
+            if (st != LBM_MC_OK) return st;
+        }
+        HIPCHECK(hipEventRecord(e1, c->stream));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1000.0 * ms / reps;
+        if (us < best) {
+            best = us;
+            bestt = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tune = bestt;
+    lbm_mc_status st = build_tiles(c);
+    if (st != LBM_MC_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto& q = c->params[0];
+        g_tune_cache[{c->lattice, c->N, q.nx, q.ny, q.nz, c->L}] = bestt;
+    }
+    // the candidates wrote f~ into prev: it no longer holds f~(t-1)
+    c->prev_valid = false;
+    if (best_us) *best_us = best;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_set_batched_mode(lbm_mc_ctx* c, int32_t one_launch) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    c->one_launch = one_launch ? 1 : 0;
+    drop_graphs(c);
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
+    if (!c) return LBM_MC_OK;
+    if (c->stream || c->dlp) hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap) hipStreamDestroy(c->cap);
+    hipFree(c->dlp);
+    hipFree(c->dflag);
+    hipFree(c->dtiles);
+    hipFree(c->dpartial);
+    hipFree(c->dtotals);
+    hipFree(c->dmu);
+    hipFree(c->dgpart);
+    hipFree(c->df0scratch);
+    delete c;
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* c, const float*, const float*, float*, double*) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* c, const float*, double*) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+// Forward kernels: the fused time step, the initial state, and the
+// observables with their FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include "collide.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lbmmc {
+
+// Work-groups are dealt to the eight XCDs round-robin by work-group id.  Map
+// the id to a "virtual" id so that the work-groups on one XCD take a
+// contiguous range of the (spatially ordered) tile list and share its halo
+// rows in their XCD's L2.  Bijective for any grid size.
+__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int k = b & 7, idx = b >> 3, per = G >> 3, rem = G & 7;
+    const int vb = k * per + (k < rem ? k : rem) + idx;
+    t0 = (int)((int64_t)vb * ntiles / G);
+    t1 = (int)((int64_t)(vb + 1) * ntiles / G);
+}
+
+template <int LAT, int NS>
+struct StepOp {
+    static constexpr int Q = Lat<LAT>::Q;
+    float* __restrict__ dst;
+    int64_t plane;
+    CollConst C;
+    bool bad;
+    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int,
+                                               int64_t own) {
+        if (!collide<LAT, NS>(P0, F, C)) bad = true;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            dst[(int64_t)(s * Q) * plane + own] = P0[s];
+#pragma unroll
+            for (int a = 1; a < Q; ++a) dst[(int64_t)(s * Q + a) * plane + own] = F[s][a];
+        }
+    }
+};
+
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
+                                              const LatParams* __restrict__ lps,
+                                              const Tile* __restrict__ tiles, int ntiles,
+                                              unsigned* __restrict__ flag) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    int t0, t1;
+    tile_range(ntiles, t0, t1);
+    bool bad = false;
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = tiles[t];
+        const LatParams& P = lps[T.lat];
+        const int x = T.x0 + (int)threadIdx.x;
+        const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+        if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
+        const GatherConst G = gather_const(P, DIM);
+        StepOp<LAT, NS> op{dst + P.base, P.plane, coll_const(P), false};
+        march<LAT, NS>(src + P.base, G, x, y, T.m0, T.m1, op);
+        bad = bad || op.bad;
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+// Initial state of one lattice: f(0) = [1 + e.u_i0/c_s^2] omega rho_i with
+// u_i0 = -g/2 (force-consistent initial velocity, zero species and mixture
+// velocity), rho_i = x_i M_i n0, evaluated in double and stored as
+// P0 = f_0 and g_a = f_a - (w_a/w_0) P0 + w_a (f_0 - P0)/(1 - w_0) in f0_out;
+// then one collision, stored in ft_out.
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps, int lat,
+                                              const double* __restrict__ x0,
+                                              float* __restrict__ f0_out,
+                                              float* __restrict__ ft_out,
+                                              unsigned* __restrict__ flag) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+    const LatParams& P = lps[lat];
+    const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+    const double* xl = x0 + P.field_base * NS;
+    const CollConst C = coll_const(P);
+    bool bad = false;
+    const double w0 = LAT == 0 ? 4.0 / 9.0 : 1.0 / 3.0;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < nodes;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(id % P.nx);
+        const int64_t r = id / P.nx;
+        const int y = (int)(r % P.ny);
+        const int z = (int)(r / P.ny);
+        const int64_t own = P.base + ((int64_t)z * P.ny + y) * P.pitch + x;
+        float P0[NS], F[NS][Q];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double rho = xl[s * nodes + id] * (double)P.M[s] * (double)P.n0;
+            const double c = (double)C.c[s], ics = (double)C.inv_cs2[s];
+            const double f0 = w0 * rho;
+            const float p0 = (float)f0;
+            const double rem = (f0 - (double)p0) / (1.0 - w0);
+            P0[s] = p0;
+            F[s][0] = 0.0f;
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                const double wa = LAT == 0 ? (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0)
+                                           : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+                const double eu = c * (double)cdot<LAT>(a, -0.5f * C.g[0], -0.5f * C.g[1],
+                                                        -0.5f * C.g[2]);
+                const double fa = wa * rho * (1.0 + ics * eu);
+                F[s][a] = (float)(fa - wa / w0 * (double)p0 + wa * rem);
+            }
+            f0_out[(int64_t)(s * Q) * P.plane + own] = p0;
+#pragma unroll
+            for (int a = 1; a < Q; ++a) f0_out[(int64_t)(s * Q + a) * P.plane + own] = F[s][a];
+        }
+        // f(0) as gather output: P0 and F_a = f_a - w_a r* = g_a
+        if (!collide<LAT, NS>(P0, F, C)) bad = true;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            ft_out[(int64_t)(s * Q) * P.plane + own] = P0[s];
+#pragma unroll
+            for (int a = 1; a < Q; ++a) ft_out[(int64_t)(s * Q + a) * P.plane + own] = F[s][a];
+        }
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+// ------------------------------------------------------------- observables
+template <int LAT, int NS>
+struct MomOp {
+    static constexpr int Q = Lat<LAT>::Q;
+    static constexpr int DIM = Lat<LAT>::DIM;
+    float* rho_out;
+    float* x_out;
+    float* u_out;
+    int64_t nodes;
+    int nx, ny, x, y;
+    CollConst C;
+    double acc[NS + 3];
+    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
+                                               int64_t) {
+        float rho[NS], dlt[NS], ue[NS][3];
+        node_moments<LAT, NS>(P0, F, C, rho, dlt, ue);
+        float R = 0.0f, n = 0.0f, U[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            R += rho[s];
+            n += rho[s] * C.invM[s];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) U[d] = fmaf(rho[s], ue[s][d], U[d]);
+        }
+        const float iR = 1.0f / R;
+        const int64_t node = DIM == 2 ? (int64_t)m * nx + x : ((int64_t)m * ny + y) * nx + x;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (rho_out) rho_out[s * nodes + node] = rho[s];
+            if (x_out) x_out[s * nodes + node] = rho[s] * C.invM[s] / n;
+            acc[s] += (double)rho[s];
+        }
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if (u_out) u_out[d * nodes + node] = U[d] * iR;
+            acc[NS + d] += (double)U[d];   // rho u = sum_i rho_i u_i^eq
+        }
+    }
+};
+
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
+                                                 const LatParams* __restrict__ lps,
+                                                 const Tile* __restrict__ tiles, int direct,
+                                                 float* rho, float* xo, float* u,
+                                                 double* __restrict__ partial, int nq) {
+    constexpr int Q = Lat<LAT>::Q;
+    constexpr int DIM = Lat<LAT>::DIM;
+    __shared__ double red[4][NS + 3];
+    const int t = blockIdx.x;
+    const Tile T = tiles[t];
+    const LatParams& P = lps[T.lat];
+    const int x = T.x0 + (int)threadIdx.x;
+    const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+    const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+    MomOp<LAT, NS> op;
+    op.rho_out = rho ? rho + P.field_base * NS : nullptr;
+    op.x_out = xo ? xo + P.field_base * NS : nullptr;
+    op.u_out = u ? u + P.field_base * DIM : nullptr;
+    op.nodes = nodes;
+    op.nx = P.nx; op.ny = P.ny; op.x = x; op.y = y;
+    op.C = coll_const(P);
+#pragma unroll
+    for (int q = 0; q < NS + 3; ++q) op.acc[q] = 0.0;
+    if (x < P.nx && (DIM == 2 || y < P.ny)) {
+        const float* lb = src + P.base;
+        if (direct) {
+            for (int m = T.m0; m < T.m1; ++m) {
+                const int64_t own = node_off<LAT>(P.pitch, P.ny, x, y, m);
+                float P0[NS], F[NS][Q];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    P0[s] = lb[(int64_t)(s * Q) * P.plane + own];
+                    F[s][0] = 0.0f;
+#pragma unroll
+                    for (int a = 1; a < Q; ++a) F[s][a] = lb[(int64_t)(s * Q + a) * P.plane + own];
+                }
+                op(P0, F, m, own);
+            }
+        } else {
+            const GatherConst G = gather_const(P, DIM);
+            march<LAT, NS>(lb, G, x, y, T.m0, T.m1, op);
+        }
+    }
+    // block reduction: wave shuffles, then the waves in a fixed order
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nwaves = (blockDim.x * blockDim.y + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NS + DIM; ++q) {
+        double v = op.acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid < NS + DIM) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[w][tid];
+        partial[(int64_t)t * nq + tid] = s;
+    }
+}
+
+// Fixed-order FP64 sum of the per-tile partials of each lattice.
+__global__ void k_reduce(const LatParams* __restrict__ lps, int nlat,
+                         const double* __restrict__ partial, int nq, double* __restrict__ totals) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nlat * nq) return;
+    const int l = id / nq, q = id % nq;
+    double s = 0.0;
+    for (int t = lps[l].tile_begin; t < lps[l].tile_end; ++t) s += partial[(int64_t)t * nq + q];
+    totals[id] = s;
+}
+
+// ---------------------------------------------------------------- launchers
+template <int LAT, int NS>
+static hipError_t launch_step_t(const Launch& L) {
+    dim3 block(L.bx, L.by);
+    hipLaunchKernelGGL((k_step<LAT, NS>), dim3(L.grid), block, 0, L.stream, L.src, L.dst, L.lp,
+                       L.tiles, L.ntiles, L.flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int lattice, int ns, const Launch& L) {
+    if (lattice == 0) {
+        if (ns == 2) return launch_step_t<0, 2>(L);
+        if (ns == 3) return launch_step_t<0, 3>(L);
+        if (ns == 4) return launch_step_t<0, 4>(L);
+    } else {
+        if (ns == 2) return launch_step_t<1, 2>(L);
+        if (ns == 3) return launch_step_t<1, 3>(L);
+        if (ns == 4) return launch_step_t<1, 4>(L);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int LAT, int NS>
+static hipError_t launch_init_t(const LatParams* lp, int lat, const LatParams& h, const double* x0,
+                                float* f0, float* ft, unsigned* flag, hipStream_t s) {
+    const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
+    int64_t blocks = (nodes + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_init<LAT, NS>), dim3((unsigned)blocks), dim3(256), 0, s, lp, lat, x0, f0,
+                       ft, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const LatParams& h,
+                       const double* x0, float* f0, float* ft, unsigned* flag, hipStream_t s) {
+    if (lattice == 0) {
+        if (ns == 2) return launch_init_t<0, 2>(lp, lat, h, x0, f0, ft, flag, s);
+        if (ns == 3) return launch_init_t<0, 3>(lp, lat, h, x0, f0, ft, flag, s);
+        if (ns == 4) return launch_init_t<0, 4>(lp, lat, h, x0, f0, ft, flag, s);
+    } else {
+        if (ns == 2) return launch_init_t<1, 2>(lp, lat, h, x0, f0, ft, flag, s);
+        if (ns == 3) return launch_init_t<1, 3>(lp, lat, h, x0, f0, ft, flag, s);
+        if (ns == 4) return launch_init_t<1, 4>(lp, lat, h, x0, f0, ft, flag, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int LAT, int NS>
+static hipError_t launch_moments_t(const Launch& L, int direct, float* rho, float* x, float* u,
+                                   double* partial, int nq) {
+    hipLaunchKernelGGL((k_moments<LAT, NS>), dim3(L.ntiles), dim3(L.bx, L.by), 0, L.stream, L.src,
+                       L.lp, L.tiles, direct, rho, x, u, partial, nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int lattice, int ns, const Launch& L, int direct, float* rho, float* x,
+                          float* u, double* partial, int nq) {
+    if (lattice == 0) {
+        if (ns == 2) return launch_moments_t<0, 2>(L, direct, rho, x, u, partial, nq);
+        if (ns == 3) return launch_moments_t<0, 3>(L, direct, rho, x, u, partial, nq);
+        if (ns == 4) return launch_moments_t<0, 4>(L, direct, rho, x, u, partial, nq);
+    } else {
+        if (ns == 2) return launch_moments_t<1, 2>(L, direct, rho, x, u, partial, nq);
+        if (ns == 3) return launch_moments_t<1, 3>(L, direct, rho, x, u, partial, nq);
+        if (ns == 4) return launch_moments_t<1, 4>(L, direct, rho, x, u, partial, nq);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
+                         double* totals, hipStream_t s) {
+    const int n = nlat * nq;
+    hipLaunchKernelGGL(k_reduce, dim3((n + 255) / 256), dim3(256), 0, s, lp, nlat, partial, nq,
+                       totals);
+    return hipGetLastError();
+}
+
+}  // namespace lbmmc

@@ -1,0 +1,213 @@
+"""Python face of the HIP library: argument marshalling only.  torch supplies
+device memory and the stream; every step of the method runs in the library's
+kernels."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Params, check, lib
+
+
+LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
+                   19: [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12}
+
+
+def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
+                walls=(False, False, False), n0=0.0):
+    """Fill one lbm_mc_params struct."""
+    p = Params()
+    p.lattice = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}[lattice] if isinstance(lattice, str) \
+        else int(lattice)
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    N = len(masses)
+    p.n_species = N
+    for a in range(3):
+        p.bc[a] = _lib.WALL if walls[a] else _lib.PERIODIC
+    for i in range(N):
+        p.molar_mass[i] = float(masses[i])
+        for j in range(N):
+            p.diff[i][j] = float(diff[i][j]) if i != j else 0.0
+    p.tau1 = float(tau1)
+    for a in range(3):
+        p.g[a] = float(g[a])
+    p.n0 = float(n0 or 0.0)
+    p.forcing = 0
+    p.reserved = 0
+    return p
+
+
+def params_from_workload(w):
+    return make_params(w.lattice, w.nx, w.ny, w.nz, w.masses, w.diff, w.tau1, w.g,
+                       w.walls, w.n0 or 0.0)
+
+
+def _arr(params):
+    if isinstance(params, Params):
+        params = [params]
+    arr = (Params * len(params))(*params)
+    return arr, len(params)
+
+
+def layout(params):
+    arr, L = _arr(params)
+    total = ctypes.c_int64()
+    offs = (ctypes.c_int64 * L)()
+    pitch = (ctypes.c_int32 * L)()
+    fields = (ctypes.c_int64 * L)()
+    check(lib.lbm_mc_layout(arr, L, ctypes.byref(total), offs, pitch, fields))
+    return total.value, list(offs), list(pitch), list(fields)
+
+
+def check_problem(params, x0):
+    arr, L = _arr(params)
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    lam = ctypes.c_double()
+    st = lib.lbm_mc_check(arr, L, x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          ctypes.byref(lam))
+    return st, lam.value, lib.lbm_mc_last_error().decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class LbmMc:
+    """One context of the library over torch-owned population buffers.
+
+    params: one Params or a list (batched); x0: float64 array [L*N*nodes]
+    (or any array whose C-order flattening is that)."""
+
+    def __init__(self, params, x0, device="cuda", stream=None):
+        self._arr, self.L = _arr(params)
+        self.params = list(self._arr)
+        self.total, self.offsets, self.pitch, self.field_offsets = layout(self.params)
+        self.N = self.params[0].n_species
+        self.lattice = self.params[0].lattice
+        self.Q = 9 if self.lattice == _lib.D2Q9 else 19
+        self.dim = 2 if self.lattice == _lib.D2Q9 else 3
+        self.nodes = [p.nx * p.ny * p.nz for p in self.params]
+        self.device = torch.device(device)
+        self.fa = torch.empty(self.total, dtype=torch.float32, device=self.device)
+        self.fb = torch.empty(self.total, dtype=torch.float32, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(-1))
+        self._x0 = x0
+        self.ctx = ctypes.c_void_p()
+        check(lib.lbm_mc_init(self._arr, self.L,
+                              x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _ptr(self.fa), _ptr(self.fb), self.total,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)))
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, n=1):
+        check(lib.lbm_mc_step(self.ctx, int(n)))
+
+    def sync(self):
+        check(lib.lbm_mc_sync(self.ctx))
+
+    @property
+    def t(self):
+        t = ctypes.c_int64()
+        check(lib.lbm_mc_state(self.ctx, None, None, ctypes.byref(t)))
+        return t.value
+
+    def buffers(self):
+        """(cur, prev) torch views: f~(t) and f~(t-1)."""
+        cur, prev = ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib.lbm_mc_state(self.ctx, ctypes.byref(cur), ctypes.byref(prev), None))
+        a = self.fa if cur.value == self.fa.data_ptr() else self.fb
+        b = self.fb if a is self.fa else self.fa
+        return a, b
+
+    def raw(self, which="cur", lattice=0):
+        """[N, Q, nz, ny, nx] view of one lattice's stored state: plane 0 of a
+        species is its rest population P0 = f~_0, plane a >= 1 is
+        g_a = f~_a - (w_a/w_0) P0."""
+        buf = self.buffers()[0 if which == "cur" else 1]
+        p = self.params[lattice]
+        n = self.N * self.Q * p.nz * p.ny * self.pitch[lattice]
+        v = buf[self.offsets[lattice]: self.offsets[lattice] + n]
+        return v.view(self.N, self.Q, p.nz, p.ny, self.pitch[lattice])[..., : p.nx]
+
+    def populations(self, which="cur", lattice=0):
+        """Post-collision populations f~ [N, Q, nz, ny, nx] of one lattice, in
+        float64, rebuilt from the stored state: f~_0 = P0 and
+        f~_a = (w_a/w_0) P0 + g_a for a >= 1."""
+        r = self.raw(which, lattice).double()
+        w = torch.tensor(LATTICE_WEIGHTS[self.Q], dtype=torch.float64, device=r.device)
+        p0 = r[:, :1]
+        f = (w / w[0])[None, :, None, None, None] * p0 + r
+        f[:, 0] = p0[:, 0]
+        return f
+
+    def moments(self, fields=True):
+        """Observables of f(t): dict with 'rho', 'x' [sum_l N*nodes], 'u'
+        [sum_l dim*nodes] (device tensors) and 'mass' [L, N], 'momentum' [L, dim]
+        (numpy float64)."""
+        tot = sum(self.nodes)
+        out = {}
+        if fields:
+            out["rho"] = torch.empty(tot * self.N, dtype=torch.float32, device=self.device)
+            out["x"] = torch.empty(tot * self.N, dtype=torch.float32, device=self.device)
+            out["u"] = torch.empty(tot * self.dim, dtype=torch.float32, device=self.device)
+        mass = np.zeros((self.L, self.N))
+        mom = np.zeros((self.L, self.dim))
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib.lbm_mc_moments(self.ctx, _ptr(out.get("rho")), _ptr(out.get("x")),
+                                 _ptr(out.get("u")), mass.ctypes.data_as(dp),
+                                 mom.ctypes.data_as(dp)))
+        out["mass"] = mass
+        out["momentum"] = mom
+        return out
+
+    def field(self, out, name, lattice=0):
+        """Reshape a node field of `moments()` for one lattice: [k, nz, ny, nx]."""
+        p = self.params[lattice]
+        k = self.N if name in ("rho", "x") else self.dim
+        off = self.field_offsets[lattice] * k
+        n = self.nodes[lattice] * k
+        return out[name][off: off + n].view(k, p.nz, p.ny, p.nx)
+
+    def restore(self, cur, prev, t):
+        check(lib.lbm_mc_restore(self.ctx, _ptr(cur), _ptr(prev), int(t)))
+
+    # ------------------------------------------------------------------ tuning
+    def set_tuning(self, block_x=0, block_y=0, rows=0, persistent=-1):
+        check(lib.lbm_mc_set_tuning(self.ctx, block_x, block_y, rows, persistent))
+
+    def get_tuning(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(lib.lbm_mc_get_tuning(self.ctx, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def autotune(self, reps=5):
+        """Pick the fastest execution shape.  Invalidates f~(t-1); callers that
+        need moments right away should build a fresh context (the choice is
+        cached for the process)."""
+        best = ctypes.c_double()
+        check(lib.lbm_mc_autotune(self.ctx, int(reps), ctypes.byref(best)))
+        return best.value
+
+    def set_batched_mode(self, one_launch):
+        check(lib.lbm_mc_set_batched_mode(self.ctx, int(one_launch)))
+
+    # ----------------------------------------------------------------- adjoint
+    def adjoint_step(self, f_prev, lam_in, lam_out, grad):
+        check(lib.lbm_mc_adjoint_step(self.ctx, _ptr(f_prev), _ptr(lam_in), _ptr(lam_out),
+                                      _ptr(grad)))
+
+    def adjoint_init(self, lam0, grad):
+        check(lib.lbm_mc_adjoint_init(self.ctx, _ptr(lam0), _ptr(grad)))
+
+    def close(self):
+        if self.ctx:
+            lib.lbm_mc_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

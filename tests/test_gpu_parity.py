@@ -1,0 +1,203 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars (spec tolerance for the FP32 state): mole fractions within 1e-5 of
+the oracle; per-species mass drift below 1e-6; post-collision populations
+within 2e-6 of the oracle relative to the largest population (FP32 rounding
+of a few dozen steps).  Integer-like properties (determinism, independence of
+the execution shape, resume) are bit-exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_workloads as W
+from oracle import evd
+from oracle.lattice import DTYPE
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+X_TOL = 1e-5
+MASS_TOL = 1e-6
+F_RTOL = 2e-6
+
+
+def _lbm():
+    from paper_2504_07059_amd import lbm
+    return lbm
+
+
+def _oracle_model(w, ny=None):
+    return evd.Model(w.lattice, w.nx, w.ny if ny is None else ny, w.nz, w.masses,
+                     torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+
+
+def _announce(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+def _gpu_run(w, steps, tuning=None, x0=None):
+    lbm = _lbm()
+    x0 = w.x0() if x0 is None else x0
+    sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
+    if tuning:
+        sim.set_tuning(*tuning)
+    m0 = sim.moments(fields=False)["mass"][0].copy()
+    sim.step(steps)
+    out = sim.moments()
+    sim.sync()
+    return sim, out, m0
+
+
+def _compare(w, steps, tuning=None, ftol=F_RTOL):
+    m = _oracle_model(w)
+    f = evd.initial_populations(m, torch.tensor(w.x0(), dtype=DTYPE))
+    f = evd.run(m, f, steps)
+    ob = evd.observables(m, f)
+    ft = evd.collide(m, f)
+    sim, out, m0 = _gpu_run(w, steps, tuning)
+    xg = sim.field(out, "x").double().cpu()
+    dx = (xg - ob["x"]).abs().max().item()
+    fg = sim.populations("cur").double().cpu()
+    df = ((fg - ft).abs().max() / ft.abs().max()).item()
+    drift = np.abs(out["mass"][0] / m0 - 1).max()
+    dmass = np.abs(out["mass"][0] / ob["mass"].numpy() - 1).max()
+    sim.close()
+    return dx, df, drift, dmass
+
+
+def _wk(name, lattice, shape, masses, walls, g, steps=24, seed=11, diff=None):
+    N = len(masses)
+    if diff is None:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(0.06, 0.1, size=(N, N))
+        diff = ((d + d.T) / 2).tolist()
+    return W.Workload(name, lattice, *shape, masses, diff, 1.0, list(g), list(walls), steps,
+                      "random", seed=seed)
+
+
+SMALL = [
+    _wk("d2q9_n3_xwall", "D2Q9", (300, 37, 1), [2.0, 28.0, 44.0], (True, False, False),
+        (1e-5, 2e-6, 0),
+        diff=W.pairs_to_matrix(W.load_accepted()["ternary_gravity"]["pairs"], 3)),
+    _wk("d2q9_n2_ywall", "D2Q9", (130, 40, 1), [1.0, 3.0], (False, True, False), (0, -2e-5, 0)),
+    _wk("d2q9_n4_periodic", "D2Q9", (70, 33, 1), [1.0, 2.0, 3.0, 4.0], (False, False, False),
+        (3e-6, 1e-6, 0)),
+    _wk("d2q9_n2_equal", "D2Q9", (65, 9, 1), [1.0, 1.0], (True, False, False), (1e-5, 0, 0)),
+    _wk("d3q19_n4_zwall", "D3Q19", (40, 21, 19), [1.0, 2.0, 3.0, 4.0], (False, False, True),
+        (0, 0, -1e-5), steps=16),
+    _wk("d3q19_n2_xwall", "D3Q19", (23, 18, 17), [1.0, 5.0], (True, False, False),
+        (2e-5, 0, 0), steps=16),
+    _wk("d3q19_n3_ywall", "D3Q19", (20, 26, 11), [1.0, 2.0, 6.0], (False, True, False),
+        (0, 1e-5, 0), steps=16),
+]
+
+
+@pytest.mark.parametrize("w", SMALL, ids=[w.name for w in SMALL])
+def test_small_lattices_match_oracle(w):
+    """Several tiles and ragged edges in every direction, every wall axis,
+    2-4 species, gravity, random compositions."""
+    _announce(w.name)
+    dx, df, drift, dmass = _compare(w, w.steps)
+    assert dx < X_TOL, dx
+    assert df < F_RTOL, df
+    assert drift < MASS_TOL, drift
+    assert dmass < MASS_TOL, dmass
+
+
+@pytest.mark.parametrize("tuning", [(64, 1, 4, 0), (128, 1, 7, 0), (256, 1, 64, 0),
+                                    (64, 1, 16, 40)])
+def test_execution_shape_does_not_change_results(tuning):
+    """Each node's arithmetic is independent of the tiling, so every execution
+    shape (work-group width, layers per thread, persistent grid) gives
+    bit-identical populations."""
+    w = SMALL[0]
+    _announce(f"{w.name} tuning {tuning}")
+    ref, _, _ = _gpu_run(w, 9, tuning=(256, 1, 16, 0))
+    a = ref.populations("cur").clone()
+    sim, _, _ = _gpu_run(w, 9, tuning=tuning)
+    b = sim.populations("cur")
+    assert torch.equal(a, b)
+
+
+def test_determinism_and_resume_are_bitwise():
+    w = SMALL[4]
+    _announce(f"{w.name} resume")
+    lbm = _lbm()
+    p = lbm.params_from_workload(w)
+    a = lbm.LbmMc(p, w.x0())
+    a.step(10)
+    cur, prev = (t.clone() for t in a.buffers())
+    a.step(7)
+    b = lbm.LbmMc(p, w.x0())
+    b.restore(cur, prev, 10)
+    b.step(7)
+    assert torch.equal(a.populations("cur"), b.populations("cur"))
+    ma, mb = a.moments(), b.moments()
+    assert torch.equal(ma["x"], mb["x"])
+    assert np.array_equal(ma["mass"], mb["mass"])
+
+
+def test_moments_at_t0_are_the_initial_state():
+    w = SMALL[0]
+    _announce(f"{w.name} t=0 moments")
+    lbm = _lbm()
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    out = sim.moments()
+    x = sim.field(out, "x").double().cpu().numpy()
+    assert np.abs(x - w.x0()).max() < 1e-6
+    u = sim.field(out, "u").abs().max().item()
+    assert u < 1e-8      # force-consistent initial state has zero velocity
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN planted from the host in the state is reported by sync()."""
+    w = SMALL[3]
+    _announce("nonfinite flag")
+    lbm = _lbm()
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    cur, prev = sim.buffers()
+    cur[100] = float("nan")
+    sim.step(2)
+    with pytest.raises(lbm._lib.LbmError) as e:
+        sim.sync()
+    assert e.value.status == 5
+
+
+# ------------------------------------------------------------ full workloads
+def _golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as fh:
+        return json.load(fh)
+
+
+def test_binary_erf_full_2000_steps():
+    """Binary Loschmidt tube 200x4, 2000 steps, against the oracle (computed
+    on one row, exact for a y-uniform state)."""
+    w = W.binary_erf()
+    _announce(w.name)
+    g = _golden("binary_erf")["checkpoints"]["2000"]
+    sim, out, m0 = _gpu_run(w, 2000)
+    x = sim.field(out, "x").double().cpu().numpy()          # [N, 1, ny, nx]
+    ref = np.array(g["x"])                                    # [N, nx]
+    assert np.abs(x[:, 0] - ref[:, None, :]).max() < X_TOL
+    assert np.abs(out["mass"][0] / m0 - 1).max() < MASS_TOL
+
+
+@pytest.mark.parametrize("steps", [100, 2000, 20000])
+def test_ternary_gravity_full_size(steps):
+    """Ternary tube 1024x64 with gravity (masses 2:28:44, seeded D), at the
+    execution shape the benchmark uses, against the oracle at 100, 2000 and
+    20000 steps; FP64 mass totals drift less than 1e-6."""
+    w = W.ternary_gravity()
+    _announce(f"{w.name} {steps} steps")
+    g = _golden("ternary_gravity")["checkpoints"][str(steps)]
+    sim, out, m0 = _gpu_run(w, steps)
+    x = sim.field(out, "x").double().cpu().numpy()
+    ref = np.array(g["x"])
+    err = np.abs(x[:, 0] - ref[:, None, :]).max()
+    assert err < X_TOL, err
+    assert np.abs(out["mass"][0] / m0 - 1).max() < MASS_TOL
+    want = np.array(g["mass_per_row"]) * w.ny
+    assert np.abs(out["mass"][0] / want - 1).max() < MASS_TOL
