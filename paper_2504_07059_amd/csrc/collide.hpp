@@ -55,6 +55,13 @@ __device__ __forceinline__ float cdot(int a, float vx, float vy, float vz) {
     return r;
 }
 
+// 1/x as the hardware reciprocal refined by one Newton step (about 1 ulp;
+// x is a positive, normal density-like quantity wherever this is used).
+__device__ __forceinline__ float rcp_nr(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Cross-relaxation solve.  For the pairs (i, j), i < j, that share the larger
 // index j, eq. (relation_tauij_diff_coeff) with the index convention of the
 // ternary solution of Sec. 4.1 reads (D + d rho^T) y = R_j d with
@@ -76,10 +83,10 @@ __device__ __forceinline__ void tau_solve(const float (&rho)[NS], float R, float
         float q = 0.0f;
 #pragma unroll
         for (int i = 0; i < j; ++i) {
-            iE[i] = 1.0f / (rho[j] + n * C.K[i][j]);
+            iE[i] = rcp_nr(fmaf(n, C.K[i][j], rho[j]));
             q += rho[i] * iE[i];
         }
-        const float t = Rj / (1.0f + q);
+        const float t = Rj * rcp_nr(1.0f + q);
 #pragma unroll
         for (int i = 0; i < j; ++i) {
             y[i][j] = t * iE[i];
@@ -116,7 +123,7 @@ __device__ __forceinline__ void node_moments(const float (&P0)[NS],
         const float r = fmaf(P0[s], L::inv_w0, sf);
         rho[s] = r;
         if (fabsf(r) > kRhoTiny) {
-            const float cr = C.c[s] / r;
+            const float cr = C.c[s] * rcp_nr(r);
             ue[s][0] = fmaf(jx, cr, 0.5f * C.g[0]);
             ue[s][1] = fmaf(jy, cr, 0.5f * C.g[1]);
             ue[s][2] = fmaf(jz, cr, 0.5f * C.g[2]);
@@ -158,9 +165,9 @@ __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         R += rho[s];
-        n += rho[s] * C.invM[s];
+        n = fmaf(rho[s], C.invM[s], n);
     }
-    const float iR = 1.0f / R;
+    const float iR = rcp_nr(R);
     float U[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -186,28 +193,41 @@ __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>
             for (int d = 0; d < 3; ++d) V[d] = fmaf(wij, ue[i][d] - ue[j][d], V[d]);
         }
         const float c = C.c[i], ics = C.inv_cs2[i], itau = C.inv_tau[i], fp = C.fpref[i];
-        const float du0 = ue[i][0] - U[0], du1 = ue[i][1] - U[1], du2 = ue[i][2] - U[2];
-        const float udu = U[0] * du0 + U[1] * du1 + U[2] * du2;
-        const float uV = U[0] * V[0] + U[1] * V[1] + U[2] * V[2];
-        const float F0 = rho[i] * C.g[0], F1 = rho[i] * C.g[1], F2 = rho[i] * C.g[2];
-        const float uF = U[0] * F0 + U[1] * F1 + U[2] * F2;
+        float du[3], T[3], Z[3], Fc[3];
+        float udu = 0.0f, uV = 0.0f, uF = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            du[d] = ue[i][d] - U[d];
+            const float Fd = rho[i] * C.g[d];
+            udu = fmaf(U[d], du[d], udu);
+            uV = fmaf(U[d], V[d], uV);
+            uF = fmaf(U[d], Fd, uF);
+            T[d] = ics * c * U[d];                 // t_a = c_a . T = e.u / c_s^2
+            Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
+            Fc[d] = c * Fd;                         // c_a . Fc = e.F
+        }
         const float b0 = -0.5f * uu * ics;
+        const float z0 = fmaf(itau, udu, -uV);
         float sgt = 0.0f;
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
+            // f^(eq) - w rho = w rho [t (1 + t/2) + b0],  t = e.u/c_s^2
+            // f~ - w rho = h + (feqd - h)/tau
+            //            + feq/c_s^2 [ (e.du - u.du)/tau - (e.V - u.V) ]     (f^(0), Omega^ij)
+            //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.F + t e.F ]      (S)
             const float wr = L::w(a) * rho[i];
-            const float eu = c * cdot<LAT>(a, U[0], U[1], U[2]);
-            const float edu = c * cdot<LAT>(a, du0, du1, du2);
-            const float eV = c * cdot<LAT>(a, V[0], V[1], V[2]);
-            const float eF = c * cdot<LAT>(a, F0, F1, F2);
-            // f^(eq) - w rho, f^(eq), f^(0) - w rho
-            const float feqd = wr * fmaf(ics * eu, fmaf(0.5f * ics, eu, 1.0f), b0);
-            const float feq = wr + feqd;
-            const float f0d = fmaf(feq * ics, edu - udu, feqd);
-            const float cross = -feq * ics * (eV - uV);
-            const float S = L::w(a) * (ics * (eF - uF) + ics * ics * eu * eF);
+            const float t = cdot<LAT>(a, T[0], T[1], T[2]);
+            const float feqd = wr * fmaf(t, fmaf(0.5f, t, 1.0f), b0);
+            const float A = (wr + feqd) * ics;
+            const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
+            const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
+            const float Sp = fmaf(t, eF, eF - uF);
             const float h = fmaf(-L::w(a), dlt[i], F[i][a]);   // f_a - w_a rho
-            const float gt = fmaf(-itau, h - f0d, h) + fmaf(fp, S, cross);
+            // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
+            // rounded coefficients of the latter do not sum to exactly 1, which
+            // scales the equilibrium by a constant factor every step and drifts
+            // the composition systematically
+            const float gt = fmaf(itau, feqd - h, h) + fmaf(A, yv, (fp * ics * L::w(a)) * Sp);
             F[i][a] = gt;
             sgt += gt;
         }

@@ -64,8 +64,15 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
             return fail(LBM_MC_ERR_INVALID, "lattice %d: nx, ny, nz must be >= 1", l);
         if (q.lattice == LBM_MC_D2Q9 && q.nz != 1)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: D2Q9 needs nz = 1", l);
-        if ((int64_t)q.nx * q.ny * q.nz > (int64_t)1 << 31)
-            return fail(LBM_MC_ERR_UNSUPPORTED, "lattice %d: more than 2^31 nodes", l);
+        {
+            const int64_t pitch = (q.nx + 31) / 32 * 32;
+            const int64_t floats = pitch * q.ny * q.nz * (int64_t)q.n_species *
+                                   (q.lattice == LBM_MC_D2Q9 ? 9 : 19);
+            if (floats * 4 >= ((int64_t)1 << 31))
+                return fail(LBM_MC_ERR_UNSUPPORTED,
+                            "lattice %d: one lattice's populations exceed 2 GiB per buffer "
+                            "(%lld floats); split it or use fewer species", l, (long long)floats);
+        }
         int walls = 0;
         for (int a = 0; a < 3; ++a) {
             if (q.bc[a] != LBM_MC_PERIODIC && q.bc[a] != LBM_MC_WALL)
@@ -741,13 +748,13 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     if (reps < 1) return fail(LBM_MC_ERR_INVALID, "reps must be >= 1");
     std::vector<Tuning> cands;
     const int nm = c->DIM == 2 ? c->params[0].ny : c->params[0].nz;
-    const int rowsv[] = {4, 8, 16, 32, 64, 128};
+    const int rowsv[] = {1, 2, 4, 8, 16, 32, 64, 128};
     const int pers[] = {0, 1};
     if (c->DIM == 2) {
         for (int bx : {64, 128, 256})
             for (int r : rowsv)
                 for (int ps : pers) {
-                    if (r > 2 * nm && r != 4) continue;
+                    if (r > 2 * nm && r != 1) continue;
                     Tuning t;
                     t.bx = bx; t.by = 1; t.rows = r;
                     t.persistent = ps ? c->cus * (1024 / bx) : 0;

@@ -23,18 +23,17 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
 template <int LAT, int NS>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
-    float* __restrict__ dst;
-    int64_t plane;
+    Buf D;
     CollConst C;
     bool bad;
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int,
-                                               int64_t own) {
+                                               unsigned own) {
         if (!collide<LAT, NS>(P0, F, C)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            dst[(int64_t)(s * Q) * plane + own] = P0[s];
+            stb(D, s * Q, own, P0[s]);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) dst[(int64_t)(s * Q + a) * plane + own] = F[s][a];
+            for (int a = 1; a < Q; ++a) stb(D, s * Q + a, own, F[s][a]);
         }
     }
 };
@@ -55,8 +54,9 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
-        StepOp<LAT, NS> op{dst + P.base, P.plane, coll_const(P), false};
-        march<LAT, NS>(src + P.base, G, x, y, T.m0, T.m1, op);
+        const int64_t lf = P.plane * NS * Lat<LAT>::Q;
+        StepOp<LAT, NS> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false};
+        march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
     if (bad) atomicOr(flag, 1u);
@@ -136,7 +136,7 @@ struct MomOp {
     CollConst C;
     double acc[NS + 3];
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
-                                               int64_t) {
+                                               unsigned) {
         float rho[NS], dlt[NS], ue[NS][3];
         node_moments<LAT, NS>(P0, F, C, rho, dlt, ue);
         float R = 0.0f, n = 0.0f, U[3] = {0.0f, 0.0f, 0.0f};
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
         const float* lb = src + P.base;
         if (direct) {
             for (int m = T.m0; m < T.m1; ++m) {
-                const int64_t own = node_off<LAT>(P.pitch, P.ny, x, y, m);
+                const int64_t own = (DIM == 2 ? (int64_t)m * P.pitch : ((int64_t)m * P.ny + y) * P.pitch) + x;
                 float P0[NS], F[NS][Q];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -200,11 +200,11 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
 #pragma unroll
                     for (int a = 1; a < Q; ++a) F[s][a] = lb[(int64_t)(s * Q + a) * P.plane + own];
                 }
-                op(P0, F, m, own);
+                op(P0, F, m, 0u);
             }
         } else {
             const GatherConst G = gather_const(P, DIM);
-            march<LAT, NS>(lb, G, x, y, T.m0, T.m1, op);
+            march<LAT, NS>(make_buf(lb, P.plane * NS * Q, P.plane), G, x, y, T.m0, T.m1, op);
         }
     }
     // block reduction: wave shuffles, then the waves in a fixed order
