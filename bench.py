@@ -22,7 +22,9 @@ The JSON line also carries
   accuracy:     max |x_s - x_s(oracle)| of the timed run when the oracle result
                 for that step count is stored, and the FP64 mass drift;
   hbm_scale:    the same physics on a 16384 x 1024 tube (3.6 GB per step), where
-                the lattice no longer fits the 256 MB last-level cache.
+                the lattice no longer fits the 256 MB last-level cache;
+  batched:      512 independent ternary tubes of uneven sizes (22.8 M nodes),
+                one persistent launch per step against one launch per tube.
 """
 import argparse
 import json
@@ -130,6 +132,50 @@ def cpu_baseline(w, budget_s=15.0):
                       f"({torch.get_num_threads()} threads)"}
 
 
+def time_batched(steps, warmup):
+    """The 512-tube batch: one persistent launch per step (autotuned shape) and,
+    for comparison, one launch per tube per step, both under captured graphs."""
+    import numpy as np
+    import torch
+    import lbm_workloads as W
+    from paper_2504_07059_amd import lbm
+    tubes = W.batched_tubes()
+    params = [lbm.params_from_workload(w) for w in tubes]
+    x0 = W.concat_x0(tubes)
+    nodes = sum(w.nodes for w in tubes)
+    tmp = lbm.LbmMc(params, x0)
+    tmp.autotune(reps=3)
+    tmp.close()
+    sim = lbm.LbmMc(params, x0)
+    m0 = sim.moments(fields=False)["mass"].copy()
+    res = {}
+    for mode in (1, 0):
+        sim.set_batched_mode(mode)
+        sim.step(warmup)
+        sim.sync()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(sim.stream)
+        sim.step(steps)
+        ev1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        res[mode] = ms
+    drift = float(np.abs(sim.moments(fields=False)["mass"] / m0 - 1).max())
+    tune = sim.get_tuning()
+    sim.close()
+    per_launch = bytes_per_species_node("D2Q9") * nodes * 3
+    out = {"workload": "batched_512_ternary_tubes", "lattices": len(tubes), "nodes": nodes,
+           "steps": steps, "tuning": list(tune), "mass_drift": drift}
+    for mode, key in ((1, "one_launch"), (0, "launch_per_lattice")):
+        ms = res[mode]
+        out[key] = {"value": nodes * 3 * steps / (ms * 1e3), "unit": "MLUPS x species",
+                    "ms_per_step": ms / steps,
+                    "achieved_GBs": per_launch / (ms * 1e-3 / steps) / 1e9}
+    return out
+
+
 def roofline(w, ms, steps):
     per_launch = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     avg_s = ms * 1e-3 / steps
@@ -147,6 +193,7 @@ def main():
     ap.add_argument("--workload", default="ternary_gravity_1024x64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-scale companion run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-tube batch")
     ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -189,7 +236,7 @@ def main():
     }
     if not args.no_hbm and w.name.startswith("ternary_gravity_1024"):
         wh = workload("c1_hbm")
-        s2, o2, ms2, wall2, drift2 = time_gpu(wh, wh.steps, 20)
+        s2, o2, ms2, wall2, drift2 = time_gpu(wh, wh.steps, 20, autotune=True)
         t2 = s2.get_tuning()
         s2.close()
         line["hbm_scale"] = {
@@ -198,6 +245,8 @@ def main():
             "unit": "MLUPS x species", "ms_per_step": ms2 / wh.steps,
             "roofline": roofline(wh, ms2, wh.steps), "mass_drift": drift2,
             "tuning": list(t2)}
+    if not args.no_batched and w.name.startswith("ternary_gravity_1024"):
+        line["batched"] = time_batched(200, 20)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -213,6 +213,12 @@ def batched_tubes(count=512, steps=10000):
     return out
 
 
+def concat_x0(workloads):
+    """Initial mole fractions of a batch, flattened lattice after lattice in the
+    [lattice][species][z][y][x] order the batched interface expects."""
+    return np.concatenate([w.x0().reshape(-1) for w in workloads])
+
+
 def adjoint_tube(nx=512, ny=64, steps=4000):
     """Adjoint workload: ternary tube 2:28:44, walls at the x ends, g = 1e-6;
     the true diffusivities come from seed 4, the evaluation point perturbs
