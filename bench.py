@@ -24,7 +24,15 @@ The JSON line also carries
   hbm_scale:    the same physics on a 16384 x 1024 tube (3.6 GB per step), where
                 the lattice no longer fits the 256 MB last-level cache;
   batched:      512 independent ternary tubes of uneven sizes (22.8 M nodes),
-                one persistent launch per step against one launch per tube.
+                one persistent launch per step against one launch per tube;
+  adjoint:      gradient of a mole-fraction profile misfit with respect to the
+                three pair diffusivities and g on a 512 x 64 ternary tube over
+                4000 steps (checkpoints every 100 steps, recomputation, the
+                hand-written reverse kernels): time per forward+backward step
+                against a plain forward step, and the reverse step's own HBM
+                rate (180 B per species-node: kernel A reads the state and the
+                adjoint and writes the scratch, kernel B reads the scratch and
+                writes the adjoint, 9 floats each).
 """
 import argparse
 import json
@@ -176,6 +184,75 @@ def time_batched(steps, warmup):
     return out
 
 
+def time_adjoint(steps=4000, K=100):
+    import torch
+    import lbm_workloads as W
+    from paper_2504_07059_amd import adjoint as A
+    from paper_2504_07059_amd import lbm
+    truth, ev = W.adjoint_tube(steps=steps)
+    N = ev.n_species
+    pairs = lambda w: [w.diff[i][j] for i in range(N) for j in range(i + 1, N)]
+    prob = A.Problem("D2Q9", ev.nx, ev.ny, 1, ev.masses, ev.tau1, ev.walls, ev.x0(), steps,
+                     checkpoint_every=K)
+    f64 = torch.float64
+    with torch.no_grad():
+        s = A.evolve(torch.tensor(pairs(truth), dtype=f64), torch.tensor(truth.g, dtype=f64), prob)
+        target = A.mole_fractions(s, ev.masses, 9).mean(dim=(1, 2))
+
+    def events():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # plain forward on the same lattice
+    sim = lbm.LbmMc(lbm.params_from_workload(ev), ev.x0())
+    sim.step(200)
+    sim.sync()
+    e0, e1 = events()
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1)
+    # reverse kernels alone: one segment of K steps from a recomputed sequence
+    stride = (sim.total + 63) // 64 * 64
+    seg = torch.empty((K, stride), dtype=torch.float32, device=sim.fa.device)
+    seg[0, : sim.total].copy_(sim.buffers()[0])
+    e0, e1 = events()
+    e0.record(sim.stream)
+    sim.replay(seg[0], K - 1, seg[1:])
+    e1.record(sim.stream)
+    lam_a = torch.zeros(sim.total, dtype=torch.float32, device=seg.device)
+    lam_b = torch.zeros_like(lam_a)
+    sim.view(lam_a).fill_(1e-3)
+    grad = torch.zeros(N * (N - 1) // 2 + 3, dtype=f64, device=seg.device)
+    sim.adjoint_run(seg, K, lam_a, lam_b, grad)      # warm
+    e2, e3 = events()
+    e2.record(sim.stream)
+    sim.adjoint_run(seg, K, lam_a, lam_b, grad)
+    e3.record(sim.stream)
+    torch.cuda.synchronize()
+    replay_us = e0.elapsed_time(e1) * 1e3 / (K - 1)
+    reverse_us = e2.elapsed_time(e3) * 1e3 / K
+    sim.close()
+    # whole forward + backward of the misfit
+    p_t = torch.tensor(pairs(ev), dtype=f64, requires_grad=True)
+    g_t = torch.tensor(ev.g, dtype=f64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = A.evolve(p_t, g_t, prob)
+    L = A.profile_misfit(s, ev.masses, 9, target)
+    L.backward()
+    torch.cuda.synchronize()
+    wall_fb = time.perf_counter() - t0
+    species_nodes = ev.nodes * N
+    return {"workload": f"adjoint_tube_{ev.nx}x{ev.ny}", "steps": steps, "checkpoint_every": K,
+            "forward_ms_per_step": ms_fwd / steps,
+            "fwd_bwd_ms_per_step": wall_fb * 1e3 / steps,
+            "fwd_bwd_over_forward": wall_fb * 1e3 / ms_fwd,
+            "reverse_step_us": reverse_us, "replay_step_us": replay_us,
+            "reverse_GBs": 180 * species_nodes / (reverse_us * 1e-6) / 1e9,
+            "loss": L.item(), "grad_pairs": p_t.grad.tolist(), "grad_g": g_t.grad.tolist()}
+
+
 def roofline(w, ms, steps):
     per_launch = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     avg_s = ms * 1e-3 / steps
@@ -194,7 +271,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-scale companion run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-tube batch")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default execution shape instead of the autotuned one")
+    ap.add_argument("--only", choices=["batched", "adjoint"],
+                    help="run one companion leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -205,9 +286,13 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.only:
+        res = time_batched(args.steps, args.warmup) if args.only == "batched" else time_adjoint()
+        print(json.dumps(res), flush=True)
+        return
 
     w = workload(args.workload)
-    sim, out, ms, wall, drift = time_gpu(w, args.steps, args.warmup, args.autotune)
+    sim, out, ms, wall, drift = time_gpu(w, args.steps, args.warmup, not args.no_autotune)
     tune = sim.get_tuning()
     sim.close()
     acc_dx, acc_drift = accuracy_vs_golden(w)
@@ -247,6 +332,8 @@ def main():
             "tuning": list(t2)}
     if not args.no_batched and w.name.startswith("ternary_gravity_1024"):
         line["batched"] = time_batched(200, 20)
+    if not args.no_adjoint and w.name.startswith("ternary_gravity_1024"):
+        line["adjoint"] = time_adjoint()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -22,10 +22,18 @@
  * Memory.  Population buffers are caller-owned device memory (float32); the
  * library borrows them for the lifetime of a context and never frees them.
  * Their layout, per lattice, is [species][direction][z][y][x] with the x rows
- * padded to a pitch of a multiple of 64 floats; lbm_mc_layout() gives the
+ * padded to a pitch of a multiple of 32 floats; lbm_mc_layout() gives the
  * sizes and offsets.  Several lattices (the batched form) are concatenated in
  * one buffer.  Populations are stored post-collision: after lbm_mc_init the
- * "current" buffer holds f~(0), after t steps it holds f~(t).
+ * "current" buffer holds the state s(0) of f~(0), after t steps s(t) of f~(t).
+ * The state s of a population set f~ (per species and node) is
+ *     plane 0:       P0  = f~_0                    (rest population)
+ *     plane a >= 1:  g_a = f~_a - (w_a/w_0) f~_0
+ * with w the lattice weights (D2Q9: w_0 = 4/9; D3Q19: w_0 = 1/3) and the
+ * directions in the paper's numbering (Sec. 2 for D2Q9).  The species density
+ * is rho_i = P0/w_0 + sum_{a>=1} g_a.  Keeping the small deviations g_a keeps
+ * rho_i and the momentum to the float32 precision of the deviations rather
+ * than of rho_i.
  *
  * Streams.  Every call that launches work does so asynchronously on the HIP
  * stream given to lbm_mc_init (may be NULL for the null stream).  Calls that
@@ -184,26 +192,54 @@ lbm_mc_status lbm_mc_state(lbm_mc_ctx* ctx, float** cur, float** prev, int64_t* 
 lbm_mc_status lbm_mc_restore(lbm_mc_ctx* ctx, const float* cur, const float* prev, int64_t t);
 
 /*
- * One reverse step of the discrete adjoint (single-lattice contexts).  With
- * Phi = C o S the map f~(t-1) -> f~(t) of lbm_mc_step (S: stream + walls,
- * C: collide), computes lam_out = (dPhi/df~(t-1))^T lam_in at f_prev = f~(t-1),
- * and ADDS the parameter gradient g^T (dPhi/dtheta) lam_in into grad.
- *   f_prev   device float, layout of a population buffer: f~(t-1).
- *   lam_in   device float, same layout: dL/df~(t).
- *   lam_out  device float, same layout: dL/df~(t-1) (written; may not alias).
- *   grad     device double [n_pairs + 3]: dL/dD_ij for the pairs i < j in
- *            row-major order (in the caller's D units), then dL/dg_x, g_y, g_z.
- * Uses a context-owned scratch buffer of the size of one population buffer.
- * Errors: LBM_MC_ERR_INVALID, LBM_MC_ERR_UNSUPPORTED (batched context), HIP.
+ * Discrete adjoint (reverse mode of the time stepping; single-lattice
+ * contexts).  With Phi the map s(t-1) -> s(t) of one lbm_mc_step on the stored
+ * states (stream with walls, collide, store), the adjoint of a loss L is
+ * lam(t) = dL/ds(t), a buffer of the population layout, and
+ * lam(t-1) = (dPhi/ds(t-1))^T lam(t).  Parameters theta are the pair
+ * diffusivities D_ij, i < j, in row-major order (in the caller's units), and
+ * the specific force g (x, y, z): grad is a device double array of
+ * n_pairs + 3 entries (n_pairs = N(N-1)/2) that the adjoint calls ADD into.
+ * The parameter gradients are summed in FP64 in a fixed order (reproducible);
+ * the adjoint fields are float32.  Buffers are device memory of the
+ * population layout, caller-owned; the padding between rows is never read.
+ *
+ * One reverse step at f_prev = s(t-1): lam_out = (dPhi/ds(t-1))^T lam_in and
+ * grad += (dPhi/dtheta)^T lam_in.  lam_out must not alias lam_in or f_prev.
+ * Uses a context-owned scratch buffer of one population buffer (allocated on
+ * first use).  Errors: LBM_MC_ERR_INVALID, LBM_MC_ERR_UNSUPPORTED (batched
+ * context), LBM_MC_ERR_HIP.
  */
 lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* ctx, const float* f_prev, const float* lam_in,
                                   float* lam_out, double* grad);
 
 /*
- * Adjoint of the initialisation f~(0) = C(f(0; g)) with respect to the
- * parameters: ADDS (d f~(0)/d theta)^T lam0 into grad (layout as above).
+ * Adjoint of the initialisation s(0) = store(C(f(0; g))) of lbm_mc_init
+ * (f(0) built from the initial mole fractions with u_i0 = -g/2, Sec. 4.2):
+ * grad += (ds(0)/dtheta)^T lam0.  The initial mole fractions are those given
+ * to lbm_mc_init (the context keeps a device copy).
  */
 lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* ctx, const float* lam0, double* grad);
+
+/*
+ * Recompute n steps from the state src into a state sequence: slot k of
+ * `states` (device, at a stride of `stride` floats >= buffer_floats, a
+ * multiple of 4, 16-byte aligned) receives the state k+1 steps after src.  The
+ * context's own buffers and step counter are not touched.  src may not be
+ * slot 0.  Bitwise identical to lbm_mc_step.
+ */
+lbm_mc_status lbm_mc_replay(lbm_mc_ctx* ctx, const float* src, int64_t n, float* states,
+                            int64_t stride);
+
+/*
+ * n reverse steps through a stored sequence: states[k] = s(t0 + k) for
+ * k = 0..n-1 (layout as lbm_mc_replay), lam_in = lam(t0 + n); on return
+ * lam_out = lam(t0) and grad has the n steps' parameter terms added.
+ * Equivalent to n lbm_mc_adjoint_step calls; uses one more context-owned
+ * buffer.  lam_out must not alias lam_in.
+ */
+lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t stride,
+                                 int64_t n, const float* lam_in, float* lam_out, double* grad);
 
 /*
  * Execution shape of the fused step.  block_x: threads along x (32..256, a

@@ -29,8 +29,7 @@ struct LatParams {
     float K[MAXS][MAXS];           // 2 M_i M_j D_ij / (M_1 c_{s,1}^2) = 6 M_i M_j D_ij
     float g[3];                    // specific body force
     float n0;                      // initial total mole number
-    double Kd[MAXS][MAXS];         // the same K in double (adjoint)
-    double dscale[MAXS][MAXS];     // d(D_ij in lattice units)/d(caller D_ij) (1 here)
+    double dscale[MAXS][MAXS];     // dK_ij/dD_ij = 6 M_i M_j (adjoint)
 };
 
 // One work item of the fused step: a lattice, the origin of a block of
@@ -65,14 +64,17 @@ hipError_t launch_moments(int lattice, int nspecies, const Launch& L, int direct
                           float* x, float* u, double* partial, int nq);
 hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
                          double* totals, hipStream_t s);
+// adjoint: kernel A (collision VJP into mu, gradient partials per tile),
+// kernel B (transposed stream mu -> lam_out), the initialisation VJP, and the
+// fixed-order sum of the partials into grad (ng = n_pairs + 3 doubles)
 hipError_t launch_adjoint(int lattice, int nspecies, const Launch& L, const float* lam_in,
                           float* mu, double* gpart, int ng);
 hipError_t launch_adjoint_stream(int lattice, int nspecies, const Launch& L, const float* mu,
                                  float* lam_out);
 hipError_t launch_adjoint_init(int lattice, int nspecies, const LatParams* lp_dev,
-                               const LatParams& lp_host, const float* f0, const float* lam0,
-                               double* gpart, int ng, hipStream_t s);
-hipError_t launch_grad_reduce(const double* gpart, int nblocks, int ng, double* grad,
-                              hipStream_t s);
+                               const LatParams& lp_host, const double* x0, const float* lam0,
+                               double* gpart, int nblocks, hipStream_t s);
+hipError_t launch_grad_reduce(const LatParams* lp_dev, const double* gpart, int nblocks, int ng,
+                              int nspecies, double* grad, hipStream_t s);
 
 }  // namespace lbmmc

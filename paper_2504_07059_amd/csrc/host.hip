@@ -357,11 +357,14 @@ struct lbm_mc_ctx {
     // captured step graphs (index: cur == bufA)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gsteps = 32;
-    // adjoint scratch
+    // adjoint: scratch population-space buffer, second adjoint buffer for
+    // adjoint_run, gradient partials, and the initial mole fractions (kept for
+    // the initialisation VJP of single-lattice contexts)
     float* dmu = nullptr;
+    float* dlam = nullptr;
     double* dgpart = nullptr;
     size_t dgpart_cap = 0;
-    float* df0scratch = nullptr;
+    double* dx0 = nullptr;
 };
 
 namespace {
@@ -417,6 +420,50 @@ lbm_mc_status build_tiles(lbm_mc_ctx* c) {
     HIPCHECK(hipStreamSynchronize(c->stream));
     drop_graphs(c);
     return LBM_MC_OK;
+}
+
+// Default execution shape: the widest work-group (fewest partial tiles) that
+// still gives at least two column blocks per compute unit, then as many layers
+// per thread as keep about eight tiles per compute unit (long marches reuse the
+// three-layer register stencil; short ones fill the chip on small lattices).
+Tuning default_tuning(const lbm_mc_params* p, int n_lattices, int dim, int cus) {
+    auto columns = [&](int bx, int by) {
+        int64_t n = 0;
+        for (int l = 0; l < n_lattices; ++l)
+            n += (int64_t)((p[l].nx + bx - 1) / bx) *
+                 (dim == 3 ? (p[l].ny + by - 1) / by : 1);
+        return n;
+    };
+    auto layers = [&]() {
+        int64_t m = 0;
+        for (int l = 0; l < n_lattices; ++l) m = std::max<int64_t>(m, dim == 3 ? p[l].nz : p[l].ny);
+        return m;
+    };
+    Tuning t;
+    if (dim == 3) {
+        t.bx = 64; t.by = 4;
+    } else {
+        t.by = 1;
+        t.bx = 64;
+        for (int bx : {256, 128}) {
+            if (columns(bx, 1) * layers() >= 2 * (int64_t)cus) {
+                t.bx = bx;
+                break;
+            }
+        }
+    }
+    const int64_t cols = columns(t.bx, t.by);
+    int64_t rows = cols * layers() / (8 * (int64_t)cus);
+    t.rows = (int)std::max<int64_t>(1, std::min<int64_t>(dim == 3 ? 16 : 32, rows));
+    t.persistent = 0;
+    return t;
+}
+
+// work-groups of the grid-stride initialisation VJP
+int init_blocks(const lbm_mc_ctx* c) {
+    const auto& q = c->params[0];
+    const int64_t nodes = (int64_t)q.nx * q.ny * q.nz;
+    return (int)std::min<int64_t>((nodes + 255) / 256, (int64_t)c->cus * 8);
 }
 
 Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
@@ -484,6 +531,48 @@ lbm_mc_status check_flag(lbm_mc_ctx* c) {
     if (f & 1u)
         return fail(LBM_MC_ERR_NONFINITE,
                     "a step produced a non-finite population (unstable parameters or input)");
+    return LBM_MC_OK;
+}
+
+lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (c->L != 1) return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: batched contexts are not supported");
+    const size_t bytes = (size_t)c->layout.total * sizeof(float);
+    if (!c->dmu) {
+        HIPCHECK(hipMalloc(&c->dmu, bytes));
+        HIPCHECK(hipMemsetAsync(c->dmu, 0, bytes, c->stream));
+    }
+    const size_t ng = (size_t)(c->N * (c->N - 1) / 2 + 3);
+    const size_t need = ng * std::max(c->htiles.size(), (size_t)init_blocks(c));
+    if (need > c->dgpart_cap) {
+        if (c->dgpart) hipFree(c->dgpart);
+        c->dgpart = nullptr;
+        HIPCHECK(hipMalloc(&c->dgpart, need * sizeof(double)));
+        c->dgpart_cap = need;
+    }
+    return LBM_MC_OK;
+}
+
+// states: n buffers of the population layout at a stride of `stride` floats
+lbm_mc_status check_sequence(lbm_mc_ctx* c, const float* states, int64_t n, int64_t stride) {
+    if (n == 0) return LBM_MC_OK;
+    if (stride < c->layout.total)
+        return fail(LBM_MC_ERR_INVALID, "stride %lld below the buffer size %lld", (long long)stride,
+                    (long long)c->layout.total);
+    if (stride % 4 || (uintptr_t)states % 16)
+        return fail(LBM_MC_ERR_INVALID, "state sequence must be 16-byte aligned (stride % 4 == 0)");
+    return LBM_MC_OK;
+}
+
+// kernel A, partial sums into grad, kernel B
+lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in, float* lam_out,
+                          double* grad) {
+    const int ng = c->N * (c->N - 1) / 2 + 3;
+    Launch L = make_launch(c, f_prev, nullptr, c->stream);
+    L.grid = L.ntiles;
+    HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, c->dmu, c->dgpart, ng));
+    HIPCHECK(launch_grad_reduce(c->dlp, c->dgpart, L.ntiles, ng, c->N, grad, c->stream));
+    HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, c->dmu, lam_out));
     return LBM_MC_OK;
 }
 
@@ -588,8 +677,7 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
                 for (int j = 0; j < nm.N; ++j) {
                     const double k = i == j ? 0.0 : 6.0 * nm.M[i] * nm.M[j] * nm.D[i][j];
                     P.K[i][j] = (float)k;
-                    P.Kd[i][j] = k;
-                    P.dscale[i][j] = 1.0;
+                    P.dscale[i][j] = i == j ? 0.0 : 6.0 * nm.M[i] * nm.M[j];
                 }
             }
         }
@@ -604,13 +692,7 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
         return bail(fail(LBM_MC_ERR_HIP, "memset failed"));
 
     // default execution shape, or a cached autotuned one
-    Tuning t;
-    if (c->DIM == 3) {
-        t.bx = 64; t.by = 4; t.rows = 16;
-    } else {
-        t.bx = p[0].nx >= 256 ? 256 : (p[0].nx >= 128 ? 128 : 64);
-        t.rows = 16;
-    }
+    Tuning t = default_tuning(p, n_lattices, c->DIM, c->cus);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find({c->lattice, c->N, p[0].nx, p[0].ny, p[0].nz, n_lattices});
@@ -631,7 +713,10 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
         e = launch_init(c->lattice, c->N, c->dlp, l, c->hlp[l], dx0, c->prev, c->cur, c->dflag,
                         c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    hipFree(dx0);
+    if (n_lattices == 1)
+        c->dx0 = dx0;
+    else
+        hipFree(dx0);
     if (e != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "init: %s", hipGetErrorString(e)));
     c->prev_valid = true;
     c->t = 0;
@@ -834,19 +919,77 @@ lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
     hipFree(c->dtotals);
     hipFree(c->dmu);
     hipFree(c->dgpart);
-    hipFree(c->df0scratch);
+    hipFree(c->dlam);
+    hipFree(c->dx0);
     delete c;
     return LBM_MC_OK;
 }
 
-lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* c, const float*, const float*, float*, double*) {
-    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
-    return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint not available in this build");
+lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* c, const float* f_prev, const float* lam_in,
+                                  float* lam_out, double* grad) {
+    lbm_mc_status st = adjoint_prepare(c);
+    if (st != LBM_MC_OK) return st;
+    if (!f_prev || !lam_in || !lam_out || !grad)
+        return fail(LBM_MC_ERR_INVALID, "adjoint_step: NULL buffer");
+    if (lam_out == lam_in || lam_out == f_prev)
+        return fail(LBM_MC_ERR_INVALID, "adjoint_step: lam_out must not alias lam_in or f_prev");
+    return adjoint_one(c, f_prev, lam_in, lam_out, grad);
 }
 
-lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* c, const float*, double*) {
+lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* c, const float* lam0, double* grad) {
+    lbm_mc_status st = adjoint_prepare(c);
+    if (st != LBM_MC_OK) return st;
+    if (!lam0 || !grad) return fail(LBM_MC_ERR_INVALID, "adjoint_init: NULL buffer");
+    const int ng = c->N * (c->N - 1) / 2 + 3;
+    const int nb = init_blocks(c);
+    HIPCHECK(launch_adjoint_init(c->lattice, c->N, c->dlp, c->hlp[0], c->dx0, lam0, c->dgpart, nb,
+                                 c->stream));
+    HIPCHECK(launch_grad_reduce(c->dlp, c->dgpart, nb, ng, c->N, grad, c->stream));
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_replay(lbm_mc_ctx* c, const float* src, int64_t n, float* states,
+                            int64_t stride) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
-    return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint not available in this build");
+    if (!src || (!states && n > 0)) return fail(LBM_MC_ERR_INVALID, "replay: NULL buffer");
+    if (n < 0) return fail(LBM_MC_ERR_INVALID, "replay: n must be >= 0");
+    lbm_mc_status st = check_sequence(c, states, n, stride);
+    if (st != LBM_MC_OK) return st;
+    const float* s = src;
+    for (int64_t k = 0; k < n; ++k) {
+        float* d = states + k * stride;
+        if (d == s) return fail(LBM_MC_ERR_INVALID, "replay: src is slot %lld", (long long)k);
+        st = launch_one(c, s, d, c->stream);
+        if (st != LBM_MC_OK) return st;
+        s = d;
+    }
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t stride, int64_t n,
+                                 const float* lam_in, float* lam_out, double* grad) {
+    lbm_mc_status st = adjoint_prepare(c);
+    if (st != LBM_MC_OK) return st;
+    if (!states || !lam_in || !lam_out || !grad)
+        return fail(LBM_MC_ERR_INVALID, "adjoint_run: NULL buffer");
+    if (n < 1) return fail(LBM_MC_ERR_INVALID, "adjoint_run: n must be >= 1");
+    if (lam_out == lam_in) return fail(LBM_MC_ERR_INVALID, "adjoint_run: lam_out aliases lam_in");
+    st = check_sequence(c, states, n, stride);
+    if (st != LBM_MC_OK) return st;
+    if (n > 1 && !c->dlam) {
+        HIPCHECK(hipMalloc(&c->dlam, (size_t)c->layout.total * sizeof(float)));
+        HIPCHECK(hipMemsetAsync(c->dlam, 0, (size_t)c->layout.total * sizeof(float), c->stream));
+    }
+    // step k (1..n) reverses the step from states[n-k] and writes lam_out when
+    // n-k is even, the context's buffer otherwise, so the last lands in lam_out
+    const float* src = lam_in;
+    for (int64_t k = 1; k <= n; ++k) {
+        float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
+        st = adjoint_one(c, states + (n - k) * stride, src, dst, grad);
+        if (st != LBM_MC_OK) return st;
+        src = dst;
+    }
+    return LBM_MC_OK;
 }
 
 }  // extern "C"

@@ -74,7 +74,6 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
                                               float* __restrict__ ft_out,
                                               unsigned* __restrict__ flag) {
     constexpr int Q = Lat<LAT>::Q;
-    using L = Lat<LAT>;
     const LatParams& P = lps[lat];
     const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
     const double* xl = x0 + P.field_base * NS;

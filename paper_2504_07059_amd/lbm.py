@@ -194,12 +194,30 @@ class LbmMc:
         check(lib.lbm_mc_set_batched_mode(self.ctx, int(one_launch)))
 
     # ----------------------------------------------------------------- adjoint
+    def view(self, buf, lattice=0):
+        """[N, Q, nz, ny, nx] view of one lattice inside any flat buffer of the
+        population layout (a state, an adjoint field)."""
+        p = self.params[lattice]
+        n = self.N * self.Q * p.nz * p.ny * self.pitch[lattice]
+        v = buf[self.offsets[lattice]: self.offsets[lattice] + n]
+        return v.view(self.N, self.Q, p.nz, p.ny, self.pitch[lattice])[..., : p.nx]
+
+    # ----------------------------------------------------------------- adjoint
     def adjoint_step(self, f_prev, lam_in, lam_out, grad):
         check(lib.lbm_mc_adjoint_step(self.ctx, _ptr(f_prev), _ptr(lam_in), _ptr(lam_out),
                                       _ptr(grad)))
 
     def adjoint_init(self, lam0, grad):
         check(lib.lbm_mc_adjoint_init(self.ctx, _ptr(lam0), _ptr(grad)))
+
+    def replay(self, src, n, states):
+        """states: [>= n, stride] float32 rows; row k <- the state k+1 steps after src."""
+        check(lib.lbm_mc_replay(self.ctx, _ptr(src), int(n), _ptr(states), states.stride(0)))
+
+    def adjoint_run(self, states, n, lam_in, lam_out, grad):
+        """Reverse n steps through rows 0..n-1 of states (= s(t0) .. s(t0+n-1))."""
+        check(lib.lbm_mc_adjoint_run(self.ctx, _ptr(states), states.stride(0), int(n),
+                                     _ptr(lam_in), _ptr(lam_out), _ptr(grad)))
 
     def close(self):
         if self.ctx:

@@ -58,7 +58,32 @@ def binary_erf():
             "checkpoints": run_tube(w, [0, 2000])}
 
 
-JOBS = {"ternary_gravity": ternary_gravity, "binary_erf": binary_erf}
+def adjoint_tube():
+    """Adjoint workload: target profile from the true diffusivities, then the
+    misfit and its gradient at the evaluation point by reverse mode (segments
+    of 100 steps) and by central differences (relative step 1e-4)."""
+    from oracle import adjoint as OA
+    truth, ev = W.adjoint_tube()
+    tube = OA.Tube("D2Q9", ev.nx, 1, 1, ev.masses, ev.tau1, ev.walls,
+                   torch.tensor(ev.x0()[:, :, :1, :], dtype=DTYPE))
+    pt = [truth.diff[0][1], truth.diff[0][2], truth.diff[1][2]]
+    pe = [ev.diff[0][1], ev.diff[0][2], ev.diff[1][2]]
+    t0 = time.time()
+    with torch.no_grad():
+        target = OA.profile(tube, torch.tensor(pt, dtype=DTYPE),
+                            torch.tensor(truth.g, dtype=DTYPE), ev.steps)
+    print(f"  target done ({time.time() - t0:.0f} s)", flush=True)
+    L, dp, dg = OA.gradient(tube, pe, list(ev.g), target, ev.steps, segment=100)
+    print(f"  reverse mode done ({time.time() - t0:.0f} s)", flush=True)
+    fd = OA.central_fd(tube, pe, list(ev.g), target, ev.steps, h=1e-4)
+    print(f"  finite differences done ({time.time() - t0:.0f} s)", flush=True)
+    return {"workload": ev.name, "steps": ev.steps, "pairs_truth": pt, "pairs_eval": pe,
+            "g_truth": list(truth.g), "g_eval": list(ev.g), "target": target.tolist(),
+            "loss": L, "grad_pairs": dp, "grad_g": dg, "fd": fd, "fd_h": 1e-4}
+
+
+JOBS = {"ternary_gravity": ternary_gravity, "binary_erf": binary_erf,
+        "adjoint_tube": adjoint_tube}
 
 
 def main(names):
