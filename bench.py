@@ -63,18 +63,20 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_gpu(w, steps, warmup, autotune=False):
+def time_gpu(w, steps, warmup, autotune=False, tuning=None):
     import numpy as np
     import torch
     from paper_2504_07059_amd import lbm
 
     p = lbm.params_from_workload(w)
     x0 = w.x0()
-    if autotune:
+    if autotune and tuning is None:
         tmp = lbm.LbmMc(p, x0)
         tmp.autotune(reps=5)
         tmp.close()
     sim = lbm.LbmMc(p, x0)
+    if tuning is not None:
+        sim.set_tuning(*tuning)
     m0 = sim.moments(fields=False)["mass"][0].copy()
     sim.step(warmup)
     sim.sync()
@@ -95,7 +97,7 @@ def time_gpu(w, steps, warmup, autotune=False):
     return sim, out, ms, wall, drift
 
 
-def accuracy_vs_golden(w, t=20000):
+def accuracy_vs_golden(w, t=20000, tuning=None):
     """Paired accuracy gate: a fresh run of the same workload to step t (at the
     same execution shape) against the stored FP64 oracle result."""
     import numpy as np
@@ -105,6 +107,8 @@ def accuracy_vs_golden(w, t=20000):
         return None, None
     g = json.load(open(path))["checkpoints"][str(t)]
     sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    if tuning is not None:
+        sim.set_tuning(*tuning)
     m0 = sim.moments(fields=False)["mass"][0].copy()
     sim.step(t)
     out = sim.moments()
@@ -253,12 +257,53 @@ def time_adjoint(steps=4000, K=100):
             "loss": L.item(), "grad_pairs": p_t.grad.tolist(), "grad_g": g_t.grad.tolist()}
 
 
-def roofline(w, ms, steps):
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size (reads and writes nbytes per
+    launch): the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes": nbytes, "reps": reps}
+
+
+KERNEL_SOURCES = ("step.hip", "kernels.hpp", "collide.hpp", "lattice.hpp", "common.hpp")
+
+
+def measured_traffic(workload_name, tuning):
+    """HBM bytes per launch of the fused step from the committed counter
+    summaries (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one was taken for
+    this workload and execution shape from the current kernel sources; else
+    None."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_07059_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    want = ",".join(str(v) for v in tuning)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+                if (rec.get("workload") == workload_name and rec.get("tuning") == want
+                        and rec.get("kernel_sources_sha256_16") == sha):
+                    return float(rec["bytes_per_launch"])
+    return None
+
+
+def roofline(w, ms, steps, tuning=None):
     per_launch = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     avg_s = ms * 1e-3 / steps
     achieved = per_launch / avg_s / 1e9
+    traffic = measured_traffic(w.name, tuning) if tuning is not None else None
     return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
             "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
 
 
@@ -274,7 +319,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default execution shape instead of the autotuned one")
-    ap.add_argument("--only", choices=["batched", "adjoint"],
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the paired accuracy run against the stored oracle result")
+    ap.add_argument("--tuning", help="fixed execution shape bx,by,rows,persistent (no autotune)")
+    ap.add_argument("--only", choices=["batched", "adjoint", "copy"],
                     help="run one companion leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -287,15 +335,19 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     if args.only:
-        res = time_batched(args.steps, args.warmup) if args.only == "batched" else time_adjoint()
+        if args.only == "copy":
+            res = copy_calibration()
+        else:
+            res = time_batched(args.steps, args.warmup) if args.only == "batched" else time_adjoint()
         print(json.dumps(res), flush=True)
         return
 
     w = workload(args.workload)
-    sim, out, ms, wall, drift = time_gpu(w, args.steps, args.warmup, not args.no_autotune)
+    fixed = [int(v) for v in args.tuning.split(",")] if args.tuning else None
+    sim, out, ms, wall, drift = time_gpu(w, args.steps, args.warmup, not args.no_autotune, fixed)
     tune = sim.get_tuning()
     sim.close()
-    acc_dx, acc_drift = accuracy_vs_golden(w)
+    acc_dx, acc_drift = (None, None) if args.no_accuracy else accuracy_vs_golden(w, tuning=tune)
     value = w.nodes * w.n_species * args.steps / (ms * 1e3)
     line = {
         "metric": "MLUPS x species (fused EVD-LBM step, FP32 state)",
@@ -314,7 +366,7 @@ def main():
                    "nz": w.nz, "species": w.n_species, "masses": w.masses,
                    "walls": w.walls, "g": w.g, "tuning": list(tune),
                    "parallelism": "single GPU"},
-        "roofline": roofline(w, ms, args.steps),
+        "roofline": roofline(w, ms, args.steps, tune),
         "accuracy": {"max_dx_vs_oracle_t20000": acc_dx, "mass_drift_t20000": acc_drift,
                      "mass_drift_timed_run": drift},
         "wall_s": wall,
@@ -328,7 +380,7 @@ def main():
             "workload": wh.name, "steps": wh.steps,
             "value": wh.nodes * wh.n_species * wh.steps / (ms2 * 1e3),
             "unit": "MLUPS x species", "ms_per_step": ms2 / wh.steps,
-            "roofline": roofline(wh, ms2, wh.steps), "mass_drift": drift2,
+            "roofline": roofline(wh, ms2, wh.steps, t2), "mass_drift": drift2,
             "tuning": list(t2)}
     if not args.no_batched and w.name.startswith("ternary_gravity_1024"):
         line["batched"] = time_batched(200, 20)

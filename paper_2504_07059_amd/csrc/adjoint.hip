@@ -79,9 +79,11 @@ struct AdjOp {
     }
 };
 
-// block reduction of NG doubles into partial[blockIdx]
+// Block reduction of NG doubles, ADDED into this work-group's own partials
+// (each slot has one writer, and the reverse steps of a sequence run in
+// stream order, so the per-tile sums accumulate deterministically).
 template <int NG>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NG], double* __restrict__ out) {
+__device__ __forceinline__ void block_reduce_add(double (&acc)[NG], double* __restrict__ out) {
     __shared__ double red[4][NG];
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int lane = tid & 63, wave = tid >> 6;
@@ -97,7 +99,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NG], double* __
     if (tid < NG) {
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w) s += red[w][tid];
-        out[tid] = s;
+        out[tid] += s;
     }
 }
 
@@ -124,7 +126,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
         const GatherConst G = gather_const(P, DIM);
         march<LAT, NS>(make_buf(fprev + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
     }
-    block_reduce_store<NG>(op.acc, gpart + (int64_t)blockIdx.x * NG);
+    block_reduce_add<NG>(op.acc, gpart + (int64_t)blockIdx.x * NG);
 }
 
 // ------------------------------------------------------------------ kernel B
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(256) k_adj_init(const LatParams* __restrict__ 
 #pragma unroll
         for (int d = 0; d < 3; ++d) acc[k + d] += (double)dg[d];
     }
-    block_reduce_store<NG>(acc, gpart + (int64_t)blockIdx.x * NG);
+    block_reduce_add<NG>(acc, gpart + (int64_t)blockIdx.x * NG);
 }
 
 // Fixed-order sum of the per-block partials (one work-group of 256 threads:

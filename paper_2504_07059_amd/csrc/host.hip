@@ -564,14 +564,27 @@ lbm_mc_status check_sequence(lbm_mc_ctx* c, const float* states, int64_t n, int6
     return LBM_MC_OK;
 }
 
-// kernel A, partial sums into grad, kernel B
-lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in, float* lam_out,
-                          double* grad) {
+// Per-tile FP64 gradient partials: cleared before a sequence of reverse steps,
+// accumulated by every kernel A of the sequence, summed into grad once.
+lbm_mc_status grad_clear(lbm_mc_ctx* c, int nblocks) {
+    const size_t ng = (size_t)(c->N * (c->N - 1) / 2 + 3);
+    HIPCHECK(hipMemsetAsync(c->dgpart, 0, ng * nblocks * sizeof(double), c->stream));
+    return LBM_MC_OK;
+}
+
+lbm_mc_status grad_sum(lbm_mc_ctx* c, int nblocks, double* grad) {
+    const int ng = c->N * (c->N - 1) / 2 + 3;
+    HIPCHECK(launch_grad_reduce(c->dlp, c->dgpart, nblocks, ng, c->N, grad, c->stream));
+    return LBM_MC_OK;
+}
+
+// kernel A (partials accumulated per tile), kernel B
+lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in,
+                          float* lam_out) {
     const int ng = c->N * (c->N - 1) / 2 + 3;
     Launch L = make_launch(c, f_prev, nullptr, c->stream);
     L.grid = L.ntiles;
     HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, c->dmu, c->dgpart, ng));
-    HIPCHECK(launch_grad_reduce(c->dlp, c->dgpart, L.ntiles, ng, c->N, grad, c->stream));
     HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, c->dmu, lam_out));
     return LBM_MC_OK;
 }
@@ -933,19 +946,23 @@ lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* c, const float* f_prev, const floa
         return fail(LBM_MC_ERR_INVALID, "adjoint_step: NULL buffer");
     if (lam_out == lam_in || lam_out == f_prev)
         return fail(LBM_MC_ERR_INVALID, "adjoint_step: lam_out must not alias lam_in or f_prev");
-    return adjoint_one(c, f_prev, lam_in, lam_out, grad);
+    const int nt = (int)c->htiles.size();
+    st = grad_clear(c, nt);
+    if (st == LBM_MC_OK) st = adjoint_one(c, f_prev, lam_in, lam_out);
+    if (st == LBM_MC_OK) st = grad_sum(c, nt, grad);
+    return st;
 }
 
 lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* c, const float* lam0, double* grad) {
     lbm_mc_status st = adjoint_prepare(c);
     if (st != LBM_MC_OK) return st;
     if (!lam0 || !grad) return fail(LBM_MC_ERR_INVALID, "adjoint_init: NULL buffer");
-    const int ng = c->N * (c->N - 1) / 2 + 3;
     const int nb = init_blocks(c);
+    st = grad_clear(c, nb);
+    if (st != LBM_MC_OK) return st;
     HIPCHECK(launch_adjoint_init(c->lattice, c->N, c->dlp, c->hlp[0], c->dx0, lam0, c->dgpart, nb,
                                  c->stream));
-    HIPCHECK(launch_grad_reduce(c->dlp, c->dgpart, nb, ng, c->N, grad, c->stream));
-    return LBM_MC_OK;
+    return grad_sum(c, nb, grad);
 }
 
 lbm_mc_status lbm_mc_replay(lbm_mc_ctx* c, const float* src, int64_t n, float* states,
@@ -982,14 +999,17 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t str
     }
     // step k (1..n) reverses the step from states[n-k] and writes lam_out when
     // n-k is even, the context's buffer otherwise, so the last lands in lam_out
+    const int nt = (int)c->htiles.size();
+    st = grad_clear(c, nt);
+    if (st != LBM_MC_OK) return st;
     const float* src = lam_in;
     for (int64_t k = 1; k <= n; ++k) {
         float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
-        st = adjoint_one(c, states + (n - k) * stride, src, dst, grad);
+        st = adjoint_one(c, states + (n - k) * stride, src, dst);
         if (st != LBM_MC_OK) return st;
         src = dst;
     }
-    return LBM_MC_OK;
+    return grad_sum(c, nt, grad);
 }
 
 }  // extern "C"

@@ -225,15 +225,26 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
     }
 }
 
-// Fixed-order FP64 sum of the per-tile partials of each lattice.
-__global__ void k_reduce(const LatParams* __restrict__ lps, int nlat,
-                         const double* __restrict__ partial, int nq, double* __restrict__ totals) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nlat * nq) return;
-    const int l = id / nq, q = id % nq;
-    double s = 0.0;
-    for (int t = lps[l].tile_begin; t < lps[l].tile_end; ++t) s += partial[(int64_t)t * nq + q];
-    totals[id] = s;
+// Fixed-order FP64 sum of the per-tile partials of each lattice: one
+// work-group per lattice, thread t takes tiles begin+t, begin+t+256, ..., then
+// a fixed shuffle and LDS tree (reproducible run to run).
+__global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lps, int nlat,
+                                                const double* __restrict__ partial, int nq,
+                                                double* __restrict__ totals) {
+    __shared__ double red[4];
+    const int l = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t0 = lps[l].tile_begin, t1 = lps[l].tile_end;
+    for (int q = 0; q < nq; ++q) {
+        double v = 0.0;
+        for (int t = t0 + tid; t < t1; t += 256) v += partial[(int64_t)t * nq + q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        if (tid == 0) totals[(int64_t)l * nq + q] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -307,9 +318,7 @@ hipError_t launch_moments(int lattice, int ns, const Launch& L, int direct, floa
 
 hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
                          double* totals, hipStream_t s) {
-    const int n = nlat * nq;
-    hipLaunchKernelGGL(k_reduce, dim3((n + 255) / 256), dim3(256), 0, s, lp, nlat, partial, nq,
-                       totals);
+    hipLaunchKernelGGL(k_reduce, dim3(nlat), dim3(256), 0, s, lp, nlat, partial, nq, totals);
     return hipGetLastError();
 }
 
