@@ -25,6 +25,8 @@ The JSON line also carries
                 the lattice no longer fits the 256 MB last-level cache;
   batched:      512 independent ternary tubes of uneven sizes (22.8 M nodes),
                 one persistent launch per step against one launch per tube;
+  d3q19:        the 3-D layer workload (D3Q19, 4 species, 256 x 128 x 128,
+                152 B per species-node), 200 steps at the autotuned shape;
   adjoint:      gradient of a mole-fraction profile misfit with respect to the
                 three pair diffusivities and g on a 512 x 64 ternary tube over
                 4000 steps (checkpoints every 100 steps, recomputation, the
@@ -317,6 +319,7 @@ def main():
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-scale companion run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-tube batch")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the D3Q19 layer workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default execution shape instead of the autotuned one")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -384,6 +387,16 @@ def main():
             "tuning": list(t2)}
     if not args.no_batched and w.name.startswith("ternary_gravity_1024"):
         line["batched"] = time_batched(200, 20)
+    if not args.no_3d and w.name.startswith("ternary_gravity_1024"):
+        w3 = workload("c2")
+        s3, o3, ms3, wall3, drift3 = time_gpu(w3, 200, 20, autotune=True)
+        t3 = s3.get_tuning()
+        s3.close()
+        line["d3q19"] = {
+            "workload": w3.name, "steps": 200,
+            "value": w3.nodes * w3.n_species * 200 / (ms3 * 1e3),
+            "unit": "MLUPS x species", "ms_per_step": ms3 / 200,
+            "roofline": roofline(w3, ms3, 200, t3), "mass_drift": drift3, "tuning": list(t3)}
     if not args.no_adjoint and w.name.startswith("ternary_gravity_1024"):
         line["adjoint"] = time_adjoint()
     if not args.no_cpu:

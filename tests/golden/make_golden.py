@@ -58,6 +58,24 @@ def binary_erf():
             "checkpoints": run_tube(w, [0, 2000])}
 
 
+def layer_mixing_3d_small():
+    """D3Q19 layer workload on a 16x8x32 box (z walls, interface at z = 24,
+    seeded 1 % perturbation), mole fractions at 500 and 5000 steps."""
+    w = W.layer_mixing_3d(16, 8, 32, steps=5000)
+    m = evd.Model(w.lattice, w.nx, w.ny, w.nz, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                  w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+    f = evd.initial_populations(m, torch.tensor(w.x0(), dtype=DTYPE))
+    out, t, t0 = {}, 0, time.time()
+    for cp in (500, 5000):
+        with torch.no_grad():
+            f = evd.run(m, f, cp - t)
+        t = cp
+        ob = evd.observables(m, f)
+        out[str(cp)] = {"x": ob["x"].tolist(), "mass": ob["mass"].tolist()}
+        print(f"  t={cp} done ({time.time() - t0:.0f} s)", flush=True)
+    return {"workload": w.name, "steps": w.steps, "checkpoints": out}
+
+
 def adjoint_tube():
     """Adjoint workload: target profile from the true diffusivities, then the
     misfit and its gradient at the evaluation point by reverse mode (segments
@@ -83,7 +101,7 @@ def adjoint_tube():
 
 
 JOBS = {"ternary_gravity": ternary_gravity, "binary_erf": binary_erf,
-        "adjoint_tube": adjoint_tube}
+        "adjoint_tube": adjoint_tube, "layer_mixing_3d_small": layer_mixing_3d_small}
 
 
 def main(names):
