@@ -242,24 +242,29 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t s
                                  int64_t n, const float* lam_in, float* lam_out, double* grad);
 
 /*
- * Execution shape of the fused step.  block_x: threads along x (32..256, a
- * multiple of 32); block_y: threads along y in 3-D (1 in 2-D); rows: nodes each
- * thread marches along the slowest axis; persistent: 0 = one work-group per
- * tile, >0 = that many resident work-groups looping over the tile list.
- * Rebuilds the tile list and drops captured graphs.  0 for block_x, block_y or
- * rows, and -1 for persistent, keep the current value.
+ * Execution shape of the fused step.  A tile is block_x x block_y
+ * cross-section columns (x, and y in 3-D) by `rows` layers of the slowest axis
+ * (y in 2-D, z in 3-D); block_x is 8..256 (a multiple of 8), block_y is 1 in
+ * 2-D, and block_x * block_y is 64, 128, 192 or 256.  persistent: 0 = one
+ * work-group per tile, > 0 = that many resident work-groups looping over the
+ * tile list.  variant: 0 = one thread per column carrying every species;
+ * 1 = one wavefront per species over 64 columns (block_x * block_y = 64), the
+ * species exchanging their moments through LDS.  Both give the same results.
+ * Rebuilds the tile list and drops captured graphs.  0 for block_x, block_y
+ * or rows, and -1 for persistent or variant, keep the current value.
+ * Errors: LBM_MC_ERR_INVALID for a shape outside these limits.
  */
 lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* ctx, int32_t block_x, int32_t block_y,
-                                int32_t rows, int32_t persistent);
+                                int32_t rows, int32_t persistent, int32_t variant);
 
 /* Query the execution shape in use (any pointer may be NULL). */
 lbm_mc_status lbm_mc_get_tuning(lbm_mc_ctx* ctx, int32_t* block_x, int32_t* block_y,
-                                int32_t* rows, int32_t* persistent);
+                                int32_t* rows, int32_t* persistent, int32_t* variant);
 
 /*
- * Autotuner: time `reps` steps of each candidate execution shape (state is not
- * advanced: candidates read the current buffer and write the other one) and
- * keep the fastest.  Results are cached per shape class for the process.
+ * Autotuner: time `reps` steps of each candidate execution shape, both
+ * variants (state is not advanced: candidates read the current buffer and
+ * write the other one) and keep the fastest.  Results are cached per shape class for the process.
  * best_us (may be NULL) receives the best time per step in microseconds.
  */
 lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* ctx, int32_t reps, double* best_us);

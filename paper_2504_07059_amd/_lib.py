@@ -50,8 +50,8 @@ def _load():
         "lbm_mc_adjoint_init": [vp, vp, vp],
         "lbm_mc_replay": [vp, vp, c_int64, vp, c_int64],
         "lbm_mc_adjoint_run": [vp, vp, c_int64, c_int64, vp, vp, vp],
-        "lbm_mc_set_tuning": [vp, c_int32, c_int32, c_int32, c_int32],
-        "lbm_mc_get_tuning": [vp, P(c_int32), P(c_int32), P(c_int32), P(c_int32)],
+        "lbm_mc_set_tuning": [vp, c_int32, c_int32, c_int32, c_int32, c_int32],
+        "lbm_mc_get_tuning": [vp, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32)],
         "lbm_mc_autotune": [vp, c_int32, P(c_double)],
         "lbm_mc_set_batched_mode": [vp, c_int32],
         "lbm_mc_destroy": [vp],

@@ -99,39 +99,35 @@ __device__ __forceinline__ void tau_solve(const float (&rho)[NS], float R, float
 
 constexpr float kRhoTiny = 1e-30f;
 
-// Density, force-shifted equilibrium velocity and the deviation-form inputs of
-// every species at one node.
-template <int LAT, int NS>
-__device__ __forceinline__ void node_moments(const float (&P0)[NS],
-                                             const float (&F)[NS][Lat<LAT>::Q],
-                                             const CollConst& C, float (&rho)[NS],
-                                             float (&dlt)[NS], float (&ue)[NS][3]) {
+// Density, force-shifted equilibrium velocity and the deviation-form input of
+// one species at one node (c: the species' speed).
+template <int LAT>
+__device__ __forceinline__ void species_moments(float P0, const float (&F)[Lat<LAT>::Q], float c,
+                                                const float (&g)[3], float& rho, float& dlt,
+                                                float (&ue)[3]) {
     constexpr int Q = Lat<LAT>::Q;
     using L = Lat<LAT>;
+    float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            const float v = F[s][a];
-            sf += v;
-            if (L::cx(a) == 1) jx += v; else if (L::cx(a) == -1) jx -= v;
-            if (L::cy(a) == 1) jy += v; else if (L::cy(a) == -1) jy -= v;
-            if (L::cz(a) == 1) jz += v; else if (L::cz(a) == -1) jz -= v;
-        }
-        dlt[s] = sf;
-        const float r = fmaf(P0[s], L::inv_w0, sf);
-        rho[s] = r;
-        if (fabsf(r) > kRhoTiny) {
-            const float cr = C.c[s] * rcp_nr(r);
-            ue[s][0] = fmaf(jx, cr, 0.5f * C.g[0]);
-            ue[s][1] = fmaf(jy, cr, 0.5f * C.g[1]);
-            ue[s][2] = fmaf(jz, cr, 0.5f * C.g[2]);
-        } else {
-            ue[s][0] = 0.5f * C.g[0];
-            ue[s][1] = 0.5f * C.g[1];
-            ue[s][2] = 0.5f * C.g[2];
-        }
+    for (int a = 1; a < Q; ++a) {
+        const float v = F[a];
+        sf += v;
+        if (L::cx(a) == 1) jx += v; else if (L::cx(a) == -1) jx -= v;
+        if (L::cy(a) == 1) jy += v; else if (L::cy(a) == -1) jy -= v;
+        if (L::cz(a) == 1) jz += v; else if (L::cz(a) == -1) jz -= v;
+    }
+    dlt = sf;
+    const float r = fmaf(P0, L::inv_w0, sf);
+    rho = r;
+    if (fabsf(r) > kRhoTiny) {
+        const float cr = c * rcp_nr(r);
+        ue[0] = fmaf(jx, cr, 0.5f * g[0]);
+        ue[1] = fmaf(jy, cr, 0.5f * g[1]);
+        ue[2] = fmaf(jz, cr, 0.5f * g[2]);
+    } else {
+        ue[0] = 0.5f * g[0];
+        ue[1] = 0.5f * g[1];
+        ue[2] = 0.5f * g[2];
     }
 }
 
@@ -151,91 +147,130 @@ __device__ __forceinline__ float store_transform(float P0, float dlt, float sgt,
     return P0n;
 }
 
-// Collision of one node.  On return P0[s] holds the new stored rest
-// population and F[s][a] (a >= 1) the stored deviations g_a.  Returns false
-// if a result is not finite.
-template <int LAT, int NS>
-__device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
-                                        const CollConst& C) {
-    constexpr int Q = Lat<LAT>::Q;
-    using L = Lat<LAT>;
-    float rho[NS], dlt[NS], ue[NS][3];
-    node_moments<LAT, NS>(P0, F, C, rho, dlt, ue);
-    float R = 0.0f, n = 0.0f;
+// Mixture quantities of one node: rho, n, 1/rho, u and u.u.
+struct Mix {
+    float R, n, iR, U[3], uu;
+};
+
+template <int NS>
+__device__ __forceinline__ Mix mixture(const float (&rho)[NS], const float (&ue)[NS][3],
+                                       const CollConst& C) {
+    Mix x;
+    x.R = 0.0f;
+    x.n = 0.0f;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        R += rho[s];
-        n = fmaf(rho[s], C.invM[s], n);
+        x.R += rho[s];
+        x.n = fmaf(rho[s], C.invM[s], x.n);
     }
-    const float iR = rcp_nr(R);
-    float U[3] = {0.0f, 0.0f, 0.0f};
+    x.iR = rcp_nr(x.R);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x.U[d] = 0.0f;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) U[d] = fmaf(rho[s], ue[s][d], U[d]);
+        for (int d = 0; d < 3; ++d) x.U[d] = fmaf(rho[s], ue[s][d], x.U[d]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) U[d] *= iR;
+    for (int d = 0; d < 3; ++d) x.U[d] *= x.iR;
+    x.uu = x.U[0] * x.U[0] + x.U[1] * x.U[1] + x.U[2] * x.U[2];
+    return x;
+}
 
+// friction vector of species i: V_i = sum_j (rho_j y_ij / rho)(u_i^eq - u_j^eq)
+template <int NS>
+__device__ __forceinline__ void friction(int i, const float (&rho)[NS], const float (&ue)[NS][3],
+                                         const float (&y)[NS][NS], float iR, float (&V)[3]) {
+    V[0] = V[1] = V[2] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        if (j == i) continue;
+        const float wij = rho[j] * y[i][j] * iR;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[d] = fmaf(wij, ue[i][d] - ue[j][d], V[d]);
+    }
+}
+
+// Per-species constants of one species.
+struct SpeciesConst {
+    float c, ics, itau, fp;
+};
+
+// Collision of one species at one node, given the mixture, its friction
+// vector V and its own moments.  On return P0 holds the new stored rest
+// population and F[a] (a >= 1) the stored deviations g_a.  Returns false if a
+// result is not finite.
+template <int LAT>
+__device__ __forceinline__ bool collide_species(const SpeciesConst& K, const float (&g)[3],
+                                                float rho_i, float dlt_i, const float (&ue_i)[3],
+                                                const Mix& M, const float (&V)[3], float& P0,
+                                                float (&F)[Lat<LAT>::Q]) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+    const float c = K.c, ics = K.ics, itau = K.itau, fp = K.fp;
+    float du[3], T[3], Z[3], Fc[3];
+    float udu = 0.0f, uV = 0.0f, uF = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        du[d] = ue_i[d] - M.U[d];
+        const float Fd = rho_i * g[d];
+        udu = fmaf(M.U[d], du[d], udu);
+        uV = fmaf(M.U[d], V[d], uV);
+        uF = fmaf(M.U[d], Fd, uF);
+        T[d] = ics * c * M.U[d];               // t_a = c_a . T = e.u / c_s^2
+        Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
+        Fc[d] = c * Fd;                         // c_a . Fc = e.F
+    }
+    const float b0 = -0.5f * M.uu * ics;
+    const float z0 = fmaf(itau, udu, -uV);
+    float sgt = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        // f^(eq) - w rho = w rho [t (1 + t/2) + b0],  t = e.u/c_s^2
+        // f~ - w rho = h + (feqd - h)/tau
+        //            + feq/c_s^2 [ (e.du - u.du)/tau - (e.V - u.V) ]     (f^(0), Omega^ij)
+        //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.F + t e.F ]      (S)
+        const float wr = L::w(a) * rho_i;
+        const float t = cdot<LAT>(a, T[0], T[1], T[2]);
+        const float feqd = wr * fmaf(t, fmaf(0.5f, t, 1.0f), b0);
+        const float A = (wr + feqd) * ics;
+        const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
+        const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
+        const float Sp = fmaf(t, eF, eF - uF);
+        const float h = fmaf(-L::w(a), dlt_i, F[a]);   // f_a - w_a rho
+        // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
+        // rounded coefficients of the latter do not sum to exactly 1, which
+        // scales the equilibrium by a constant factor every step and drifts
+        // the composition systematically
+        const float gt = fmaf(itau, feqd - h, h) + fmaf(A, yv, (fp * ics * L::w(a)) * Sp);
+        F[a] = gt;
+        sgt += gt;
+    }
+    float e;
+    P0 = store_transform<LAT>(P0, dlt_i, sgt, e);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) F[a] = fmaf(L::w(a), e, F[a]);
+    return isfinite(sgt) && isfinite(P0);
+}
+
+// Collision of one node, all species.  On return P0[s] holds the new stored
+// rest population and F[s][a] (a >= 1) the stored deviations g_a.  Returns
+// false if a result is not finite.
+template <int LAT, int NS>
+__device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
+                                        const CollConst& C) {
+    float rho[NS], dlt[NS], ue[NS][3];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) species_moments<LAT>(P0[s], F[s], C.c[s], C.g, rho[s], dlt[s], ue[s]);
+    const Mix M = mixture<NS>(rho, ue, C);
     float y[NS][NS];
-    tau_solve<NS>(rho, R, n, C, y);
-
-    const float uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
-    bool ok = isfinite(R);
+    tau_solve<NS>(rho, M.R, M.n, C, y);
+    bool ok = isfinite(M.R);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-        // friction vector V_i = sum_j (rho_j y_ij / rho)(u_i^eq - u_j^eq)
-        float V[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if (j == i) continue;
-            const float wij = rho[j] * y[i][j] * iR;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) V[d] = fmaf(wij, ue[i][d] - ue[j][d], V[d]);
-        }
-        const float c = C.c[i], ics = C.inv_cs2[i], itau = C.inv_tau[i], fp = C.fpref[i];
-        float du[3], T[3], Z[3], Fc[3];
-        float udu = 0.0f, uV = 0.0f, uF = 0.0f;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            du[d] = ue[i][d] - U[d];
-            const float Fd = rho[i] * C.g[d];
-            udu = fmaf(U[d], du[d], udu);
-            uV = fmaf(U[d], V[d], uV);
-            uF = fmaf(U[d], Fd, uF);
-            T[d] = ics * c * U[d];                 // t_a = c_a . T = e.u / c_s^2
-            Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
-            Fc[d] = c * Fd;                         // c_a . Fc = e.F
-        }
-        const float b0 = -0.5f * uu * ics;
-        const float z0 = fmaf(itau, udu, -uV);
-        float sgt = 0.0f;
-#pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            // f^(eq) - w rho = w rho [t (1 + t/2) + b0],  t = e.u/c_s^2
-            // f~ - w rho = h + (feqd - h)/tau
-            //            + feq/c_s^2 [ (e.du - u.du)/tau - (e.V - u.V) ]     (f^(0), Omega^ij)
-            //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.F + t e.F ]      (S)
-            const float wr = L::w(a) * rho[i];
-            const float t = cdot<LAT>(a, T[0], T[1], T[2]);
-            const float feqd = wr * fmaf(t, fmaf(0.5f, t, 1.0f), b0);
-            const float A = (wr + feqd) * ics;
-            const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
-            const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
-            const float Sp = fmaf(t, eF, eF - uF);
-            const float h = fmaf(-L::w(a), dlt[i], F[i][a]);   // f_a - w_a rho
-            // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
-            // rounded coefficients of the latter do not sum to exactly 1, which
-            // scales the equilibrium by a constant factor every step and drifts
-            // the composition systematically
-            const float gt = fmaf(itau, feqd - h, h) + fmaf(A, yv, (fp * ics * L::w(a)) * Sp);
-            F[i][a] = gt;
-            sgt += gt;
-        }
-        float e;
-        P0[i] = store_transform<LAT>(P0[i], dlt[i], sgt, e);
-#pragma unroll
-        for (int a = 1; a < Q; ++a) F[i][a] = fmaf(L::w(a), e, F[i][a]);
-        ok = ok && isfinite(sgt) && isfinite(P0[i]);
+        float V[3];
+        friction<NS>(i, rho, ue, y, M.iR, V);
+        const SpeciesConst K{C.c[i], C.inv_cs2[i], C.inv_tau[i], C.fpref[i]};
+        ok = collide_species<LAT>(K, C.g, rho[i], dlt[i], ue[i], M, V, P0[i], F[i]) && ok;
     }
     return ok;
 }

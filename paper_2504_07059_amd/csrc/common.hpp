@@ -50,7 +50,8 @@ struct Launch {
     const Tile* tiles;
     int32_t ntiles;
     int32_t grid;        // work-groups launched (== ntiles when not persistent)
-    int32_t bx, by;      // work-group shape
+    int32_t bx, by;      // work-group shape (columns)
+    int32_t split;       // 0: one thread per column, all species; 1: one wave per species
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };

@@ -321,11 +321,12 @@ Layout make_layout(const lbm_mc_params* p, int32_t L) {
 }
 
 struct Tuning {
-    int bx = 256, by = 1, rows = 32, persistent = 0;
+    int bx = 256, by = 1, rows = 32, persistent = 0, split = 0;
 };
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, Tuning> g_tune_cache;
+// (the cache key: lattice, species, nx, ny, nz of the first lattice, lattice count)
 
 }  // namespace
 
@@ -476,6 +477,7 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.grid = c->tune.persistent > 0 ? std::min(L.ntiles, c->tune.persistent) : L.ntiles;
     L.bx = c->tune.bx;
     L.by = c->tune.by;
+    L.split = c->tune.split;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -815,29 +817,34 @@ lbm_mc_status lbm_mc_restore(lbm_mc_ctx* c, const float* cur, const float* prev,
 }
 
 lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* c, int32_t bx, int32_t by, int32_t rows,
-                                int32_t persistent) {
+                                int32_t persistent, int32_t variant) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     Tuning t = c->tune;
     if (bx) t.bx = bx;
     if (by) t.by = by;
     if (rows) t.rows = rows;
     if (persistent >= 0) t.persistent = persistent;
-    if (t.bx < 32 || t.bx > 256 || t.bx % 32) return fail(LBM_MC_ERR_INVALID, "block_x must be 32..256, multiple of 32");
+    if (variant >= 0) t.split = variant;
+    if (t.split != 0 && t.split != 1) return fail(LBM_MC_ERR_INVALID, "variant must be 0 or 1");
+    if (t.bx < 8 || t.bx > 256 || t.bx % 8) return fail(LBM_MC_ERR_INVALID, "block_x must be 8..256, multiple of 8");
     if (c->DIM == 2 && t.by != 1) return fail(LBM_MC_ERR_INVALID, "block_y must be 1 in 2-D");
     if (t.by < 1 || t.bx * t.by > 256 || (t.bx * t.by) % 64)
         return fail(LBM_MC_ERR_INVALID, "block_x*block_y must be 64, 128, 192 or 256");
+    if (t.split && t.bx * t.by != 64)
+        return fail(LBM_MC_ERR_INVALID, "the species-split variant needs block_x*block_y = 64");
     if (t.rows < 1) return fail(LBM_MC_ERR_INVALID, "rows must be >= 1");
     c->tune = t;
     return build_tiles(c);
 }
 
 lbm_mc_status lbm_mc_get_tuning(lbm_mc_ctx* c, int32_t* bx, int32_t* by, int32_t* rows,
-                                int32_t* persistent) {
+                                int32_t* persistent, int32_t* variant) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (bx) *bx = c->tune.bx;
     if (by) *by = c->tune.by;
     if (rows) *rows = c->tune.rows;
     if (persistent) *persistent = c->tune.persistent;
+    if (variant) *variant = c->tune.split;
     return LBM_MC_OK;
 }
 
@@ -845,19 +852,27 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (reps < 1) return fail(LBM_MC_ERR_INVALID, "reps must be >= 1");
     std::vector<Tuning> cands;
-    const int nm = c->DIM == 2 ? c->params[0].ny : c->params[0].nz;
+    int nm = 0;
+    for (const auto& q : c->params) nm = std::max(nm, c->DIM == 2 ? q.ny : q.nz);
     const int rowsv[] = {1, 2, 4, 8, 16, 32, 64, 128};
-    const int pers[] = {0, 1};
     if (c->DIM == 2) {
         for (int bx : {64, 128, 256})
             for (int r : rowsv)
-                for (int ps : pers) {
+                for (int ps : {0, 1}) {
                     if (r > 2 * nm && r != 1) continue;
                     Tuning t;
                     t.bx = bx; t.by = 1; t.rows = r;
                     t.persistent = ps ? c->cus * (1024 / bx) : 0;
                     cands.push_back(t);
                 }
+        for (int r : rowsv)
+            for (int ps : {0, 1}) {
+                if (r > 2 * nm && r != 1) continue;
+                Tuning t;
+                t.bx = 64; t.by = 1; t.rows = r; t.split = 1;
+                t.persistent = ps ? c->cus * 8 : 0;
+                cands.push_back(t);
+            }
     } else {
         for (int bx : {32, 64, 128})
             for (int by : {1, 2, 4, 8})
@@ -868,6 +883,13 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
                     t.bx = bx; t.by = by; t.rows = r; t.persistent = 0;
                     cands.push_back(t);
                 }
+        for (int bx : {16, 32, 64})
+            for (int r : {4, 8, 16, 32, 64}) {
+                if (r > 2 * nm && r != 4) continue;
+                Tuning t;
+                t.bx = bx; t.by = 64 / bx; t.rows = r; t.persistent = 0; t.split = 1;
+                cands.push_back(t);
+            }
     }
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));

@@ -185,194 +185,269 @@ __device__ __forceinline__ GatherConst gather_const(const LatParams& P, int dim)
             : (Fr::p1(a) < 0) ? hpass<LAT, 0, -1>(B, pidx, CEN, col, L)                   \
                               : hpass<LAT, 0, 0>(B, pidx, CEN, col, L)))
 
-// Forward pull gather of one column through layers [m0, m1); calls
-// op(P0, F, m, own) for every layer m (own: byte offset of the node).
-template <int LAT, int NS, class Op>
-__device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x, int y, int m0,
-                                      int m1, Op& op) {
+// Per-column geometry of a gather (shared by the joint and per-species forms).
+struct ColGeom {
+    Col col;
+    int sx, sy;            // wall side of the column (-1, 0, +1) on x / y
+    unsigned colbase;      // byte offset of the column in layer 0
+    unsigned lsb;          // bytes per layer
+    bool wx, wy, wm;       // walls on x / y / the marching axis
+};
+
+template <int LAT>
+__device__ __forceinline__ ColGeom col_geom(const GatherConst& G, int x, int y) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    ColGeom g;
+    g.wx = G.wall_axis == 0;
+    g.wy = DIM == 3 && G.wall_axis == 1;
+    g.wm = G.wall_axis == Frame<LAT>::MA;
+    const int xm = nbr(x, -1, G.nx, g.wx), xp = nbr(x, 1, G.nx, g.wx);
+    g.col.sxm = xm < 0;
+    g.col.sxp = xp < 0;
+    g.col.bxm = xm < 0 ? kSolid : (unsigned)(xm - x) * 4u;
+    g.col.bxp = xp < 0 ? kSolid : (unsigned)(xp - x) * 4u;
+    g.col.bym = g.col.byp = 0u;
+    g.col.sym = g.col.syp = false;
+    if constexpr (DIM == 3) {
+        const int ym = nbr(y, -1, G.ny, g.wy), yp = nbr(y, 1, G.ny, g.wy);
+        g.col.sym = ym < 0;
+        g.col.syp = yp < 0;
+        g.col.bym = ym < 0 ? kSolid : (unsigned)((ym - y) * G.pitch) * 4u;
+        g.col.byp = yp < 0 ? kSolid : (unsigned)((yp - y) * G.pitch) * 4u;
+    }
+    g.sx = g.wx ? (x == 0 ? -1 : (x == G.nx - 1 ? 1 : 0)) : 0;
+    g.sy = g.wy ? (y == 0 ? -1 : (y == G.ny - 1 ? 1 : 0)) : 0;
+    g.colbase = (unsigned)((DIM == 2 ? 0 : y * G.pitch) + x) * 4u;
+    g.lsb = (unsigned)G.lstride * 4u;
+    return g;
+}
+
+// byte offset of the column in layer ml (kSolid beyond a wall)
+__device__ __forceinline__ unsigned layer_off(const ColGeom& g, int ml) {
+    return ml < 0 ? kSolid + g.colbase : (unsigned)ml * g.lsb + g.colbase;
+}
+
+// Species 1 (c = 1) at layer m: exact shift.  f_a(O) = f~_a(O - c_a), or
+// f~_abar(O) when O - c_a is solid (halfway bounce-back); written without
+// branches: a solid source reads the rest population at O itself
+// (difference 0) and the plane of the opposite direction.
+template <int LAT>
+__device__ __forceinline__ void shift_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
+                                            int m, unsigned own, float& P0,
+                                            float (&F)[Lat<LAT>::Q]) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
     constexpr int Q = La::Q;
     constexpr int DIM = La::DIM;
-    const bool wx = G.wall_axis == 0;
-    const bool wy = DIM == 3 && G.wall_axis == 1;
-    const bool wm = G.wall_axis == Fr::MA;
-    Col col;
-    {
-        const int xm = nbr(x, -1, G.nx, wx), xp = nbr(x, 1, G.nx, wx);
-        col.sxm = xm < 0;
-        col.sxp = xp < 0;
-        col.bxm = xm < 0 ? kSolid : (unsigned)(xm - x) * 4u;
-        col.bxp = xp < 0 ? kSolid : (unsigned)(xp - x) * 4u;
-        col.bym = col.byp = 0u;
-        col.sym = col.syp = false;
+    const Col& col = g.col;
+    const float r0 = ldb(B, 0, own);
+    P0 = r0;
+    F[0] = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
+        unsigned src = own;
+        bool solid = false;
+        if (c0 > 0) { src += col.bxm; solid = solid || col.sxm; }
+        if (c0 < 0) { src += col.bxp; solid = solid || col.sxp; }
         if constexpr (DIM == 3) {
-            const int ym = nbr(y, -1, G.ny, wy), yp = nbr(y, 1, G.ny, wy);
-            col.sym = ym < 0;
-            col.syp = yp < 0;
-            col.bym = ym < 0 ? kSolid : (unsigned)((ym - y) * G.pitch) * 4u;
-            col.byp = yp < 0 ? kSolid : (unsigned)((yp - y) * G.pitch) * 4u;
+            if (c1 > 0) { src += col.bym; solid = solid || col.sym; }
+            if (c1 < 0) { src += col.byp; solid = solid || col.syp; }
+        }
+        if (cm != 0) {
+            const int ms = nbr(m, -cm, G.nm, g.wm);
+            solid = solid || ms < 0;
+            src += (unsigned)(ms - m) * g.lsb;
+        }
+        // the scalar offset names the lower of the two planes so that the
+        // per-lane offset stays inside the buffer in both cases
+        const int lo = a < La::opp(a) ? a : La::opp(a);
+        const unsigned sp = solid ? own : src;
+        const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * B.pb)
+                                  : src + (unsigned)((a - lo) * B.pb);
+        F[a] = fmaf(La::wr(a), ldb(B, 0, sp) - r0, ldb(B, lo, sg));
+    }
+}
+
+// Marching state of one heavier species: the marching-axis partial sums of
+// its deviation planes and the reference stencil of layers m-1, m, m+1.
+template <int LAT>
+struct Heavy {
+    float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
+    RhoLayer rl[3];
+};
+
+// Start the march of a heavier species (planes pb0 .. pb0+Q-1) at layer m0.
+template <int LAT>
+__device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, const ColGeom& g,
+                                            int pb0, const float* L, int m0, Heavy<LAT>& h) {
+    using Fr = Frame<LAT>;
+    constexpr int Q = Lat<LAT>::Q;
+    const Col& col = g.col;
+    const int lm = nbr(m0, -1, G.nm, g.wm);
+    const unsigned cm_ = layer_off(g, lm), c0_ = layer_off(g, m0);
+    h.rl[0] = rho_layer<LAT>(B, pb0, cm_, col);
+    h.rl[1] = rho_layer<LAT>(B, pb0, c0_, col);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        if (Fr::pm(a) != 0) {
+            const int pidx = pb0 + a;
+            const W3 wmar = wsel(Fr::pm(a), L);
+            const float hm = LBM_HP(cm_);
+            const float h0 = LBM_HP(c0_);
+            h.acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
+            h.acc1[a] = wmar.m * h0;
+        } else {
+            h.acc0[a] = 0.0f;
+            h.acc1[a] = 0.0f;
         }
     }
-    const int sx = wx ? (x == 0 ? -1 : (x == G.nx - 1 ? 1 : 0)) : 0;
-    const int sy = wy ? (y == 0 ? -1 : (y == G.ny - 1 ? 1 : 0)) : 0;
-    const unsigned colbase = (unsigned)((DIM == 2 ? 0 : y * G.pitch) + x) * 4u;
-    const unsigned lsb = (unsigned)G.lstride * 4u;   // bytes per layer
-    // byte offset of the column in layer ml (kSolid beyond a wall)
-    auto lay = [&](int ml) { return ml < 0 ? kSolid + colbase : (unsigned)ml * lsb + colbase; };
+}
 
-    // marching-axis partial sums of the deviation planes, and the reference
-    // stencil of layers m-1, m, m+1 (heavier species only)
-    float acc0[NS][Q], acc1[NS][Q];
-    RhoLayer rl[NS][3];
-    {
-        const int lm = nbr(m0, -1, G.nm, wm);
-        const unsigned cm_ = lay(lm), c0_ = lay(m0);
+// One layer of a heavier species: second-order interpolation plus the
+// impermeable-wall terms; side is the column's wall side on the wall axis.
+template <int LAT>
+__device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
+                                            int pb0, const float* L, unsigned own, unsigned nxt,
+                                            int side, Heavy<LAT>& h, float& P0,
+                                            float (&F)[Lat<LAT>::Q]) {
+    using Fr = Frame<LAT>;
+    using La = Lat<LAT>;
+    constexpr int Q = La::Q;
+    constexpr int DIM = La::DIM;
+    const Col& col = g.col;
+    h.rl[2] = rho_layer<LAT>(B, pb0, nxt, col);
+    const float rc = h.rl[1].c;
+    P0 = rc;
+    F[0] = 0.0f;
+    // 3-D edge directions in the cross-section need the corner
+    // x-differences of rows y-1 and y+1 of this layer
+    float cxm[2] = {0.0f, 0.0f}, cxp[2] = {0.0f, 0.0f};
+    if constexpr (DIM == 3) {
 #pragma unroll
-        for (int s = 1; s < NS; ++s) {
-            rl[s][0] = rho_layer<LAT>(B, s * Q, cm_, col);
-            rl[s][1] = rho_layer<LAT>(B, s * Q, c0_, col);
-            const float* L = G.lam[s];
+        for (int j = 0; j < 2; ++j) {
+            const unsigned rr = own + (j == 0 ? col.bym : col.byp);
+            const float cc = ldb(B, pb0, rr);
+            cxm[j] = ldb(B, pb0, rr + col.bxm) - cc;
+            cxp[j] = ldb(B, pb0, rr + col.bxp) - cc;
+        }
+    }
 #pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                if (Fr::pm(a) != 0) {
-                    const int pidx = s * Q + a;
-                    const W3 wmar = wsel(Fr::pm(a), L);
-                    const float hm = LBM_HP(cm_);
-                    const float h0 = LBM_HP(c0_);
-                    acc0[s][a] = fmaf(wmar.z, h0, wmar.m * hm);
-                    acc1[s][a] = wmar.m * h0;
-                } else {
-                    acc0[s][a] = 0.0f;
-                    acc1[s][a] = 0.0f;
-                }
+    for (int a = 1; a < Q; ++a) {
+        const int pidx = pb0 + a;
+        const W3 wxw = wsel(Fr::p0(a), L);
+        const W3 wyw = wsel(Fr::p1(a), L);
+        // reference part: delta_a = sum_k Lambda_k P0(O+k) - P0(O)
+        auto xpart = [&](const RhoLayer& r) {
+            return Fr::p0(a) != 0 ? fmaf(wxw.m, r.dxm, wxw.p * r.dxp) : 0.0f;
+        };
+        auto ypart = [&](const RhoLayer& r) {
+            return Fr::p1(a) != 0 ? fmaf(wyw.m, r.dym, wyw.p * r.dyp) : 0.0f;
+        };
+        float delta;
+        if (Fr::p0(a) != 0 && Fr::p1(a) != 0) {
+            // 3-D xy edge: nested pass over rows y-1, y, y+1 of layer m
+            const RhoLayer& r = h.rl[1];
+            float v = wyw.z * xpart(r);
+            v = fmaf(wyw.m, r.dym + fmaf(wxw.m, cxm[0], wxw.p * cxp[0]), v);
+            v = fmaf(wyw.p, r.dyp + fmaf(wxw.m, cxm[1], wxw.p * cxp[1]), v);
+            delta = v;
+        } else if (Fr::pm(a) == 0) {
+            delta = xpart(h.rl[1]) + ypart(h.rl[1]);
+        } else {
+            const W3 wmw = wsel(Fr::pm(a), L);
+            // a solid layer reads as zeros: its term is -rc
+            const RhoLayer& lo = h.rl[0];
+            const RhoLayer& hi = h.rl[2];
+            const float tlo = (lo.c - rc) + xpart(lo) + ypart(lo);
+            const float thi = (hi.c - rc) + xpart(hi) + ypart(hi);
+            const float tmid = xpart(h.rl[1]) + ypart(h.rl[1]);
+            delta = fmaf(wmw.p, thi, fmaf(wmw.m, tlo, wmw.z * tmid));
+        }
+        // deviation part
+        float Gv;
+        if (Fr::pm(a) == 0) {
+            Gv = LBM_HP(own);
+        } else {
+            const W3 wmar = wsel(Fr::pm(a), L);
+            const float hn = LBM_HP(nxt);   // 0 beyond a wall
+            Gv = fmaf(wmar.p, hn, h.acc0[a]);
+            h.acc0[a] = fmaf(wmar.z, hn, h.acc1[a]);
+            h.acc1[a] = wmar.m * hn;
+        }
+        F[a] = fmaf(La::wr(a), delta, Gv);
+    }
+    // impermeable walls (Appendix A): for a pointing away from the wall,
+    // f_a(O) += lambda_+1(c) f~_a(O) + lambda_-1(c) f~_abar(O); with
+    // f~ = (w/w_0) P0 + g and w_a = w_abar the reference part is
+    // (w_a/w_0)(lambda_+1 + lambda_-1) P0(O).
+    if (side != 0) {
+        const int axis = G.wall_axis;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const int ca = Fr::comp(a, axis);
+            if (side * ca < 0) {
+                const float ga = ldb(B, pb0 + a, own);
+                const float gb = ldb(B, pb0 + La::opp(a), own);
+                F[a] += fmaf(L[2], ga, L[0] * gb) + La::wr(a) * (L[2] + L[0]) * rc;
             }
         }
     }
+    h.rl[0] = h.rl[1];
+    h.rl[1] = h.rl[2];
+}
 
+// wall side of layer m on the column's wall axis
+template <int LAT>
+__device__ __forceinline__ int wall_side(const GatherConst& G, const ColGeom& g, int m) {
+    const int sm = g.wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
+    const int axis = G.wall_axis;
+    return axis == 0 ? g.sx : (axis == Frame<LAT>::MA ? sm : g.sy);
+}
+
+// Forward pull gather of one column through layers [m0, m1), all species;
+// calls op(P0, F, m, own) for every layer m (own: byte offset of the node).
+template <int LAT, int NS, class Op>
+__device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x, int y, int m0,
+                                      int m1, Op& op) {
+    constexpr int Q = Lat<LAT>::Q;
+    const ColGeom g = col_geom<LAT>(G, x, y);
+    Heavy<LAT> h[NS > 1 ? NS - 1 : 1];
+#pragma unroll
+    for (int s = 1; s < NS; ++s) heavy_begin<LAT>(B, G, g, s * Q, G.lam[s], m0, h[s - 1]);
     for (int m = m0; m < m1; ++m) {
-        const int mp = nbr(m, 1, G.nm, wm);
-        const int sm = wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
-        const unsigned own = lay(m);
-        const unsigned nxt = lay(mp);
+        const int mp = nbr(m, 1, G.nm, g.wm);
+        const unsigned own = layer_off(g, m);
+        const unsigned nxt = layer_off(g, mp);
+        const int side = wall_side<LAT>(G, g, m);
         float P0[NS], F[NS][Q];
-        // ------------------------------------------------ species 1: exact shift
-        // f_a(O) = f~_a(O - c_a), or f~_abar(O) when O - c_a is solid
-        // (halfway bounce-back); written without branches: a solid source
-        // reads the rest population at O itself (difference 0) and the plane
-        // of the opposite direction.
-        {
-            const float r0 = ldb(B, 0, own);
-            P0[0] = r0;
+        shift_layer<LAT>(B, G, g, m, own, P0[0], F[0]);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
-                unsigned src = own;
-                bool solid = false;
-                if (c0 > 0) { src += col.bxm; solid = solid || col.sxm; }
-                if (c0 < 0) { src += col.bxp; solid = solid || col.sxp; }
-                if constexpr (DIM == 3) {
-                    if (c1 > 0) { src += col.bym; solid = solid || col.sym; }
-                    if (c1 < 0) { src += col.byp; solid = solid || col.syp; }
-                }
-                if (cm != 0) {
-                    const int ms = nbr(m, -cm, G.nm, wm);
-                    solid = solid || ms < 0;
-                    src += (unsigned)(ms - m) * lsb;
-                }
-                // the scalar offset names the lower of the two planes so that the
-                // per-lane offset stays inside the buffer in both cases
-                const int lo = a < La::opp(a) ? a : La::opp(a);
-                const unsigned sp = solid ? own : src;
-                const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * B.pb)
-                                          : src + (unsigned)((a - lo) * B.pb);
-                F[0][a] = fmaf(La::wr(a), ldb(B, 0, sp) - r0, ldb(B, lo, sg));
-            }
-        }
-        // -------------------------------- heavier species: second-order interpolation
-#pragma unroll
-        for (int s = 1; s < NS; ++s) {
-            const float* L = G.lam[s];
-            rl[s][2] = rho_layer<LAT>(B, s * Q, nxt, col);
-            const float rc = rl[s][1].c;
-            P0[s] = rc;
-            // 3-D edge directions in the cross-section need the corner
-            // x-differences of rows y-1 and y+1 of this layer
-            float cxm[2] = {0.0f, 0.0f}, cxp[2] = {0.0f, 0.0f};
-            if constexpr (DIM == 3) {
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const unsigned rr = own + (j == 0 ? col.bym : col.byp);
-                    const float cc = ldb(B, s * Q, rr);
-                    cxm[j] = ldb(B, s * Q, rr + col.bxm) - cc;
-                    cxp[j] = ldb(B, s * Q, rr + col.bxp) - cc;
-                }
-            }
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const int pidx = s * Q + a;
-                const W3 wxw = wsel(Fr::p0(a), L);
-                const W3 wyw = wsel(Fr::p1(a), L);
-                // reference part: delta_a = sum_k Lambda_k P0(O+k) - P0(O)
-                auto xpart = [&](const RhoLayer& r) {
-                    return Fr::p0(a) != 0 ? fmaf(wxw.m, r.dxm, wxw.p * r.dxp) : 0.0f;
-                };
-                auto ypart = [&](const RhoLayer& r) {
-                    return Fr::p1(a) != 0 ? fmaf(wyw.m, r.dym, wyw.p * r.dyp) : 0.0f;
-                };
-                float delta;
-                if (Fr::p0(a) != 0 && Fr::p1(a) != 0) {
-                    // 3-D xy edge: nested pass over rows y-1, y, y+1 of layer m
-                    const RhoLayer& r = rl[s][1];
-                    float v = wyw.z * xpart(r);
-                    v = fmaf(wyw.m, r.dym + fmaf(wxw.m, cxm[0], wxw.p * cxp[0]), v);
-                    v = fmaf(wyw.p, r.dyp + fmaf(wxw.m, cxm[1], wxw.p * cxp[1]), v);
-                    delta = v;
-                } else if (Fr::pm(a) == 0) {
-                    delta = xpart(rl[s][1]) + ypart(rl[s][1]);
-                } else {
-                    const W3 wmw = wsel(Fr::pm(a), L);
-                    // a solid layer reads as zeros: its term is -rc
-                    const RhoLayer& lo = rl[s][0];
-                    const RhoLayer& hi = rl[s][2];
-                    const float tlo = (lo.c - rc) + xpart(lo) + ypart(lo);
-                    const float thi = (hi.c - rc) + xpart(hi) + ypart(hi);
-                    const float tmid = xpart(rl[s][1]) + ypart(rl[s][1]);
-                    delta = fmaf(wmw.p, thi, fmaf(wmw.m, tlo, wmw.z * tmid));
-                }
-                // deviation part
-                float Gv;
-                if (Fr::pm(a) == 0) {
-                    Gv = LBM_HP(own);
-                } else {
-                    const W3 wmar = wsel(Fr::pm(a), L);
-                    const float hn = LBM_HP(nxt);   // 0 beyond a wall
-                    Gv = fmaf(wmar.p, hn, acc0[s][a]);
-                    acc0[s][a] = fmaf(wmar.z, hn, acc1[s][a]);
-                    acc1[s][a] = wmar.m * hn;
-                }
-                F[s][a] = fmaf(La::wr(a), delta, Gv);
-            }
-            // impermeable walls (Appendix A): for a pointing away from the wall,
-            // f_a(O) += lambda_+1(c) f~_a(O) + lambda_-1(c) f~_abar(O); with
-            // f~ = (w/w_0) P0 + g and w_a = w_abar the reference part is
-            // (w_a/w_0)(lambda_+1 + lambda_-1) P0(O).
-            const int axis = G.wall_axis;
-            const int side = axis == 0 ? sx : (axis == Fr::MA ? sm : sy);
-            if (side != 0) {
-#pragma unroll
-                for (int a = 1; a < Q; ++a) {
-                    const int ca = Fr::comp(a, axis);
-                    if (side * ca < 0) {
-                        const float ga = ldb(B, s * Q + a, own);
-                        const float gb = ldb(B, s * Q + La::opp(a), own);
-                        F[s][a] += fmaf(L[2], ga, L[0] * gb) + La::wr(a) * (L[2] + L[0]) * rc;
-                    }
-                }
-            }
-            rl[s][0] = rl[s][1];
-            rl[s][1] = rl[s][2];
-        }
+        for (int s = 1; s < NS; ++s)
+            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, side, h[s - 1], P0[s], F[s]);
+        op(P0, F, m, own);
+    }
+}
+
+// The same gather for one species s (uniform over the wave) with weight
+// triple L; calls op(P0, F, m, own) with the species' values.
+template <int LAT, class Op>
+__device__ __forceinline__ void march1(const Buf& B, const GatherConst& G, int s,
+                                       const float (&L)[3], int x, int y, int m0, int m1,
+                                       Op& op) {
+    constexpr int Q = Lat<LAT>::Q;
+    const ColGeom g = col_geom<LAT>(G, x, y);
+    Heavy<LAT> h;
+    if (s > 0) heavy_begin<LAT>(B, G, g, s * Q, L, m0, h);
+    for (int m = m0; m < m1; ++m) {
+        const int mp = nbr(m, 1, G.nm, g.wm);
+        const unsigned own = layer_off(g, m);
+        const unsigned nxt = layer_off(g, mp);
+        float P0, F[Q];
+        if (s == 0)
+            shift_layer<LAT>(B, G, g, m, own, P0, F);
+        else
+            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_side<LAT>(G, g, m), h, P0, F);
         op(P0, F, m, own);
     }
 }

@@ -62,6 +62,99 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
     if (bad) atomicOr(flag, 1u);
 }
 
+// ------------------------------------------------------ species-split step
+// The same fused step with one wavefront per species: a work-group is NS
+// waves over the same 64 cross-section columns (bx * by = 64), wave s gathers
+// species s only, the waves exchange each node's (rho_s, u_s^eq) through LDS
+// (double-buffered, one barrier per layer), and each wave then forms the
+// mixture and the cross relaxation (identical arithmetic in every wave) and
+// collides and stores its own species.  A wave holds one species' marching
+// state instead of NS, so several times more waves fit on a SIMD.
+template <int LAT, int NS>
+struct SplitOp {
+    static constexpr int Q = Lat<LAT>::Q;
+    Buf D;
+    CollConst C;
+    SpeciesConst K;
+    float4 (*xch)[NS][64];   // [2][NS][64] exchange buffers in LDS
+    int s, lane;
+    bool inside, bad;
+    __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int m, unsigned own) {
+        float rho_s, dlt_s, ue_s[3];
+        species_moments<LAT>(P0, F, K.c, C.g, rho_s, dlt_s, ue_s);
+        float4 (*X)[64] = xch[m & 1];
+        X[s][lane] = make_float4(rho_s, ue_s[0], ue_s[1], ue_s[2]);
+        __syncthreads();
+        float rho[NS], ue[NS][3];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const float4 v = X[j][lane];
+            rho[j] = v.x;
+            ue[j][0] = v.y;
+            ue[j][1] = v.z;
+            ue[j][2] = v.w;
+        }
+        const Mix M = mixture<NS>(rho, ue, C);
+        float y[NS][NS];
+        tau_solve<NS>(rho, M.R, M.n, C, y);
+        // friction of the own species (s is uniform over the wave)
+        float V[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i != s) continue;
+            friction<NS>(i, rho, ue, y, M.iR, V);
+        }
+        const bool ok = collide_species<LAT>(K, C.g, rho_s, dlt_s, ue_s, M, V, P0, F) &&
+                        isfinite(M.R);
+        if (inside) {
+            stb(D, s * Q, own, P0);
+#pragma unroll
+            for (int a = 1; a < Q; ++a) stb(D, s * Q + a, own, F[a]);
+            bad = bad || !ok;
+        }
+    }
+};
+
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
+                                                    float* __restrict__ dst,
+                                                    const LatParams* __restrict__ lps,
+                                                    const Tile* __restrict__ tiles, int ntiles,
+                                                    int bx, unsigned* __restrict__ flag) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    constexpr int Q = Lat<LAT>::Q;
+    __shared__ float4 xch[2][NS][64];
+    const int lane = (int)threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    int t0, t1;
+    tile_range(ntiles, t0, t1);
+    bool bad = false;
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = tiles[t];
+        const LatParams& P = lps[T.lat];
+        const int cx = DIM == 3 ? lane % bx : lane;
+        const int cy = DIM == 3 ? lane / bx : 0;
+        int x = T.x0 + cx, y = DIM == 3 ? T.y0 + cy : 0;
+        // lanes beyond the lattice follow a valid column (every wave must
+        // reach the barriers) and store nothing
+        const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
+        x = x < P.nx ? x : P.nx - 1;
+        if (DIM == 3) y = y < P.ny ? y : P.ny - 1;
+        const GatherConst G = gather_const(P, DIM);
+        const int64_t lf = P.plane * NS * Q;
+        // the species' own constants, read with the uniform species index
+        // (scalar loads; no run-time indexing of register arrays)
+        const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
+        SplitOp<LAT, NS> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+                            SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s]},
+                            xch, s, lane, inside, false};
+        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, T.m0, T.m1, op);
+        bad = bad || op.bad;
+        __syncthreads();   // the next tile reuses the exchange buffers
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
 // Initial state of one lattice: f(0) = [1 + e.u_i0/c_s^2] omega rho_i with
 // u_i0 = -g/2 (force-consistent initial velocity, zero species and mixture
 // velocity), rho_i = x_i M_i n0, evaluated in double and stored as
@@ -137,7 +230,9 @@ struct MomOp {
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned) {
         float rho[NS], dlt[NS], ue[NS][3];
-        node_moments<LAT, NS>(P0, F, C, rho, dlt, ue);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            species_moments<LAT>(P0[s], F[s], C.c[s], C.g, rho[s], dlt[s], ue[s]);
         float R = 0.0f, n = 0.0f, U[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -256,7 +351,27 @@ static hipError_t launch_step_t(const Launch& L) {
     return hipGetLastError();
 }
 
+template <int LAT, int NS>
+static hipError_t launch_split_t(const Launch& L) {
+    hipLaunchKernelGGL((k_step_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0, L.stream, L.src,
+                       L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(int lattice, int ns, const Launch& L) {
+    if (L.split) {
+        if (L.bx * L.by != 64) return hipErrorInvalidValue;
+        if (lattice == 0) {
+            if (ns == 2) return launch_split_t<0, 2>(L);
+            if (ns == 3) return launch_split_t<0, 3>(L);
+            if (ns == 4) return launch_split_t<0, 4>(L);
+        } else {
+            if (ns == 2) return launch_split_t<1, 2>(L);
+            if (ns == 3) return launch_split_t<1, 3>(L);
+            if (ns == 4) return launch_split_t<1, 4>(L);
+        }
+        return hipErrorInvalidValue;
+    }
     if (lattice == 0) {
         if (ns == 2) return launch_step_t<0, 2>(L);
         if (ns == 3) return launch_step_t<0, 3>(L);

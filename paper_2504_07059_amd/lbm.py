@@ -174,11 +174,12 @@ class LbmMc:
         check(lib.lbm_mc_restore(self.ctx, _ptr(cur), _ptr(prev), int(t)))
 
     # ------------------------------------------------------------------ tuning
-    def set_tuning(self, block_x=0, block_y=0, rows=0, persistent=-1):
-        check(lib.lbm_mc_set_tuning(self.ctx, block_x, block_y, rows, persistent))
+    def set_tuning(self, block_x=0, block_y=0, rows=0, persistent=-1, variant=-1):
+        check(lib.lbm_mc_set_tuning(self.ctx, block_x, block_y, rows, persistent, variant))
 
     def get_tuning(self):
-        v = [ctypes.c_int32() for _ in range(4)]
+        """(block_x, block_y, rows, persistent, variant)."""
+        v = [ctypes.c_int32() for _ in range(5)]
         check(lib.lbm_mc_get_tuning(self.ctx, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 

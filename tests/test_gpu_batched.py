@@ -32,20 +32,23 @@ def _batch(tubes, **tuning):
     return sim
 
 
-@pytest.mark.parametrize("one_launch,persistent", [(1, 0), (1, 96), (0, 0)])
-def test_batched_equals_single_lattice_runs(one_launch, persistent):
+@pytest.mark.parametrize("one_launch,persistent,variant", [(1, 0, 0), (1, 96, 0), (0, 0, 0),
+                                                           (1, 96, 1)])
+def test_batched_equals_single_lattice_runs(one_launch, persistent, variant):
     """Every lattice of a batch evolves bit-identically to the same lattice
     run alone (the per-node arithmetic does not depend on the batch), in both
-    launch modes and with a persistent grid."""
+    launch modes, with a persistent grid and in both kernel variants."""
     tubes = [W.batched_tubes(count=40)[i] for i in (0, 5, 17, 23, 31, 39)]
-    _announce(f"batch of {len(tubes)} one_launch={one_launch} persistent={persistent}")
+    _announce(f"batch of {len(tubes)} one_launch={one_launch} persistent={persistent} "
+              f"variant={variant}")
     lbm = _lbm()
-    sim = _batch(tubes, block_x=64, rows=8, persistent=persistent)
+    sim = _batch(tubes, block_x=64, rows=8, persistent=persistent, variant=variant)
     sim.set_batched_mode(one_launch)
     sim.step(37)
     sim.sync()
     for l, w in enumerate(tubes):
         one = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        one.set_tuning(block_x=64, rows=8, variant=variant)    # same kernel variant
         one.step(37)
         one.sync()
         assert torch.equal(sim.raw("cur", l), one.raw("cur")), (l, w.nx, w.ny)
