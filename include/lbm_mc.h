@@ -251,7 +251,9 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t s
  * 1 = one wavefront per species over 64 columns (block_x * block_y = 64), the
  * species exchanging their moments through LDS.  Both give the same results.
  * Rebuilds the tile list and drops captured graphs.  0 for block_x, block_y
- * or rows, and -1 for persistent or variant, keep the current value.
+ * or rows, and -1 for persistent, keep the current value; variant -1 keeps
+ * the current variant if the new shape allows it, else selects variant 0.
+ * The default shape uses variant 1.
  * Errors: LBM_MC_ERR_INVALID for a shape outside these limits.
  */
 lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* ctx, int32_t block_x, int32_t block_y,

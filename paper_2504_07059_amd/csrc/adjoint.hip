@@ -11,73 +11,16 @@
 //   kernel B (per node): lam_f(t-1) = S^T mu, i.e. the gather of mu with the
 //            velocities reversed plus the transposed wall terms; stored as
 //            lam_s(t-1) = T^-T lam_f(t-1).
-// The state and adjoint are FP32; parameter gradients are summed in FP64 per
-// thread, per work-group and then over work-groups in a fixed order.
+// Both kernels run one wave per species over tiles of 64 columns (their own
+// tile list, independent of the forward step's execution shape).  The state
+// and adjoint are FP32; parameter gradients are summed in FP64 per thread,
+// per work-group and then over work-groups in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include "adjoint.hpp"
 #include "kernels.hpp"
 
 namespace lbmmc {
-
-// ------------------------------------------------------------------ kernel A
-template <int LAT, int NS>
-struct AdjOp {
-    static constexpr int Q = Lat<LAT>::Q;
-    static constexpr int NG = NS * (NS - 1) / 2 + 3;
-    Buf lam;      // lam_s(t), representation space
-    Buf mu;       // scratch, population space
-    CollConst C;
-    double acc[NG];
-    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int,
-                                               unsigned own) {
-        using L = Lat<LAT>;
-        // moments of the streamed populations f_a = w_a r* + F_a (a >= 1),
-        // f_0 = P0: sum_a w_a = 1 and sum_a c_a w_a = 0
-        float rho[NS], jm[NS][3], lt[NS][Q];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const float v = F[s][a];
-                sf += v;
-                jx += (float)L::cx(a) * v;
-                jy += (float)L::cy(a) * v;
-                jz += (float)L::cz(a) * v;
-            }
-            rho[s] = fmaf(P0[s], L::inv_w0, sf);
-            jm[s][0] = jx;
-            jm[s][1] = jy;
-            jm[s][2] = jz;
-            // lam_f = T^T lam_s: lam_f0 = lam_P0 - sum_a (w_a/w_0) lam_ga, lam_fa = lam_ga
-            float l0 = ldb(lam, s * Q, own);
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                lt[s][a] = ldb(lam, s * Q + a, own);
-                l0 = fmaf(-L::wr(a), lt[s][a], l0);
-            }
-            lt[s][0] = l0;
-        }
-        float dK[NS][NS], dg[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-#pragma unroll
-            for (int j = 0; j < NS; ++j) dK[i][j] = 0.0f;
-        collide_vjp<LAT, NS>(rho, jm, lt, C, dK, dg);
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int a = 0; a < Q; ++a) stb(mu, s * Q + a, own, lt[s][a]);
-        int k = 0;
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-#pragma unroll
-            for (int j = i + 1; j < NS; ++j) acc[k++] += (double)dK[i][j];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) acc[k + d] += (double)dg[d];
-    }
-};
 
 // Block reduction of NG doubles, ADDED into this work-group's own partials
 // (each slot has one writer, and the reverse steps of a sequence run in
@@ -103,30 +46,173 @@ __device__ __forceinline__ void block_reduce_add(double (&acc)[NG], double* __re
     }
 }
 
+// Column of a work-group's 64 lanes: x fastest over bx columns, then y (3-D).
+// Lanes beyond the lattice follow a valid column and do not store.
+template <int LAT>
+__device__ __forceinline__ bool tile_column(const Tile& T, const LatParams& P, int lane, int bx,
+                                            int& x, int& y) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    x = T.x0 + (DIM == 3 ? lane % bx : lane);
+    y = DIM == 3 ? T.y0 + lane / bx : 0;
+    const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
+    x = x < P.nx ? x : P.nx - 1;
+    if (DIM == 3) y = y < P.ny ? y : P.ny - 1;
+    return inside;
+}
+
+// ------------------------------------------------------------------ kernel A
+// One wave per species over 64 columns.  Per layer: the wave gathers f(t) of
+// its species from f~(t-1) and publishes its density and momentum in LDS;
+// every wave recomputes the node's forward collision state; each wave runs
+// its species' part of the reverse sweep and publishes its contributions to
+// the shared adjoints (u, rho, the densities and velocities, y); every wave
+// sums them in species order and runs the shared tail (mixture and
+// cross-relaxation reverse), then finishes and stores its own species' mu.
+template <int LAT, int NS>
+struct AdjSplitOp {
+    static constexpr int Q = Lat<LAT>::Q;
+    static constexpr int NG = NS * (NS - 1) / 2 + 3;
+    static constexpr int KX = 4 + 5 * NS;   // packed contribution floats per species
+    Buf lam;      // lam_s(t), representation space
+    Buf mu;       // scratch, population space
+    CollConst C;
+    float (*x1)[4][64];
+    float (*x2)[KX][64];
+    int s, lane;
+    bool inside;
+    double acc[NG];
+    __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int, unsigned own) {
+        using L = Lat<LAT>;
+        // own density and momentum (sum_a w_a = 1, sum_a c_a w_a = 0)
+        float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const float v = F[a];
+            sf += v;
+            jx += (float)L::cx(a) * v;
+            jy += (float)L::cy(a) * v;
+            jz += (float)L::cz(a) * v;
+        }
+        x1[s][0][lane] = fmaf(P0, L::inv_w0, sf);
+        x1[s][1][lane] = jx;
+        x1[s][2][lane] = jy;
+        x1[s][3][lane] = jz;
+        // lam_f = T^T lam_s: lam_f0 = lam_P0 - sum_a (w_a/w_0) lam_ga, lam_fa = lam_ga
+        float lt[Q];
+        float l0 = ldb(lam, s * Q, own);
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            lt[a] = ldb(lam, s * Q + a, own);
+            l0 = fmaf(-L::wr(a), lt[a], l0);
+        }
+        lt[0] = l0;
+        __syncthreads();
+        float rho[NS], jm[NS][3];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            rho[j] = x1[j][0][lane];
+            jm[j][0] = x1[j][1][lane];
+            jm[j][1] = x1[j][2][lane];
+            jm[j][2] = x1[j][3][lane];
+        }
+        VjpFwd<NS> f;
+        vjp_forward<NS>(rho, jm, C, f);
+        VjpAcc<NS> part;
+        vjp_zero<NS>(part);
+        float dg[3] = {0.0f, 0.0f, 0.0f};
+        float row[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i != s) continue;
+            vjp_species<LAT, NS>(i, rho, f, C, lt, part, dg);
+#pragma unroll
+            for (int j = 0; j < NS; ++j) row[j] = part.dY[i][j];
+        }
+        {
+            int k = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) x2[s][k++][lane] = part.dU[d];
+            x2[s][k++][lane] = part.dR;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) x2[s][k++][lane] = part.drho[j];
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) x2[s][k++][lane] = part.due[j][d];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) x2[s][k++][lane] = row[j];
+        }
+        __syncthreads();
+        VjpAcc<NS> A;
+        vjp_zero<NS>(A);
+#pragma unroll
+        for (int v = 0; v < NS; ++v) {
+            int k = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) A.dU[d] += x2[v][k++][lane];
+            A.dR += x2[v][k++][lane];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) A.drho[j] += x2[v][k++][lane];
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) A.due[j][d] += x2[v][k++][lane];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) A.dY[v][j] = x2[v][k++][lane];
+        }
+        float dK[NS][NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int j = 0; j < NS; ++j) dK[i][j] = 0.0f;
+        vjp_mixture<NS>(rho, f, C, A, dK);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i != s) continue;
+            vjp_finish<LAT, NS>(i, rho, f, C, A, lt, dg);
+        }
+        if (inside) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) stb(mu, s * Q + a, own, lt[a]);
+            int k = 0;
+            // every wave holds the same dL/dK: the species-0 wave adds it
+#pragma unroll
+            for (int i = 0; i < NS; ++i)
+#pragma unroll
+                for (int j = i + 1; j < NS; ++j) acc[k++] += s == 0 ? (double)dK[i][j] : 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc[k + d] += (double)dg[d];
+        }
+    }
+};
+
 template <int LAT, int NS>
 __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ fprev,
                                                      const float* __restrict__ lam,
                                                      float* __restrict__ mu,
                                                      const LatParams* __restrict__ lps,
-                                                     const Tile* __restrict__ tiles,
+                                                     const Tile* __restrict__ tiles, int bx,
                                                      double* __restrict__ gpart) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
-    constexpr int NG = NS * (NS - 1) / 2 + 3;
+    using Op = AdjSplitOp<LAT, NS>;
+    __shared__ float x1[NS][4][64];
+    __shared__ float x2[NS][Op::KX][64];
+    const int lane = (int)threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
-    const int x = T.x0 + (int)threadIdx.x;
-    const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+    int x, y;
+    const bool inside = tile_column<LAT>(T, P, lane, bx, x, y);
     const int64_t lf = P.plane * NS * Q;
-    AdjOp<LAT, NS> op{make_buf(lam + P.base, lf, P.plane), make_buf(mu + P.base, lf, P.plane),
-                      coll_const(P), {}};
+    Op op{make_buf(lam + P.base, lf, P.plane), make_buf(mu + P.base, lf, P.plane),
+          coll_const(P), x1, x2, s, lane, inside, {}};
 #pragma unroll
-    for (int q = 0; q < NG; ++q) op.acc[q] = 0.0;
-    if (x < P.nx && (DIM == 2 || y < P.ny)) {
-        const GatherConst G = gather_const(P, DIM);
-        march<LAT, NS>(make_buf(fprev + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
-    }
-    block_reduce_add<NG>(op.acc, gpart + (int64_t)blockIdx.x * NG);
+    for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    const GatherConst G = gather_const(P, DIM);
+    const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
+    march1<LAT>(make_buf(fprev + P.base, lf, P.plane), G, s, L, x, y, T.m0, T.m1, op);
+    block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
 // ------------------------------------------------------------------ kernel B
@@ -134,25 +220,28 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
 // with the velocity reversed: Lambda_{-k}(e) = Lambda_k(-e)), plus the
 // transposed wall terms; species 1 (c = 1): mu_a(X + c_a), or mu_abar(X)
 // where X + c_a is solid.  Stored as lam_s = T^-T lam_f:
-// lam_P0 = lam_f0 + sum_a (w_a/w_0) lam_fa, lam_ga = lam_fa.
+// lam_P0 = lam_f0 + sum_a (w_a/w_0) lam_fa, lam_ga = lam_fa.  One thread per
+// (column, species): species are independent here.
 template <int LAT, int NS>
 __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu,
                                                     float* __restrict__ lamout,
                                                     const LatParams* __restrict__ lps,
-                                                    const Tile* __restrict__ tiles) {
+                                                    const Tile* __restrict__ tiles, int bx) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
     constexpr int DIM = La::DIM;
     constexpr int Q = La::Q;
+    const int lane = (int)threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
-    const int x = T.x0 + (int)threadIdx.x;
-    const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
-    if (x >= P.nx || (DIM == 3 && y >= P.ny)) return;
+    int x, y;
+    if (!tile_column<LAT>(T, P, lane, bx, x, y)) return;
     const GatherConst G = gather_const(P, DIM);
     const int64_t lf = P.plane * NS * Q;
     const Buf M = make_buf(mu + P.base, lf, P.plane);
     const Buf O = make_buf(lamout + P.base, lf, P.plane);
+    const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
     const bool wx = G.wall_axis == 0, wy = DIM == 3 && G.wall_axis == 1,
                wm = G.wall_axis == Fr::MA;
     const int xm = nbr(x, -1, G.nx, wx), xp = nbr(x, 1, G.nx, wx);
@@ -161,87 +250,87 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
         ym = nbr(y, -1, G.ny, wy);
         yp = nbr(y, 1, G.ny, wy);
     }
-    const unsigned bx[3] = {xm < 0 ? kSolid : (unsigned)(xm - x) * 4u, 0u,
-                            xp < 0 ? kSolid : (unsigned)(xp - x) * 4u};
-    const unsigned by[3] = {DIM == 3 ? (ym < 0 ? kSolid : (unsigned)((ym - y) * G.pitch) * 4u) : 0u,
-                            0u,
-                            DIM == 3 ? (yp < 0 ? kSolid : (unsigned)((yp - y) * G.pitch) * 4u) : 0u};
+    const unsigned bxo[3] = {xm < 0 ? kSolid : (unsigned)(xm - x) * 4u, 0u,
+                             xp < 0 ? kSolid : (unsigned)(xp - x) * 4u};
+    const unsigned byo[3] = {DIM == 3 ? (ym < 0 ? kSolid : (unsigned)((ym - y) * G.pitch) * 4u) : 0u,
+                             0u,
+                             DIM == 3 ? (yp < 0 ? kSolid : (unsigned)((yp - y) * G.pitch) * 4u) : 0u};
     const int sx = wx ? (x == 0 ? -1 : (x == G.nx - 1 ? 1 : 0)) : 0;
     const int sy = wy ? (y == 0 ? -1 : (y == G.ny - 1 ? 1 : 0)) : 0;
     const unsigned colbase = (unsigned)((DIM == 2 ? 0 : y * G.pitch) + x) * 4u;
     const unsigned lsb = (unsigned)G.lstride * 4u;
+    const int pb0 = s * Q;
     for (int m = T.m0; m < T.m1; ++m) {
         const int mmv = nbr(m, -1, G.nm, wm), mpv = nbr(m, 1, G.nm, wm);
         const unsigned own = (unsigned)m * lsb + colbase;
-        const unsigned bm[3] = {mmv < 0 ? kSolid : (unsigned)(mmv - m) * lsb, 0u,
-                                mpv < 0 ? kSolid : (unsigned)(mpv - m) * lsb};
+        const unsigned bmo[3] = {mmv < 0 ? kSolid : (unsigned)(mmv - m) * lsb, 0u,
+                                 mpv < 0 ? kSolid : (unsigned)(mpv - m) * lsb};
         const int sm = wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
         const int axis = G.wall_axis;
         const int side = axis == 0 ? sx : (axis == Fr::MA ? sm : sy);
+        float lf_[Q];
+        lf_[0] = ldb(M, pb0, own);
+        if (s == 0) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const float* L = G.lam[s];
-            float lf_[Q];
-            lf_[0] = ldb(M, s * Q, own);
+            for (int a = 1; a < Q; ++a) {
+                // reversed shift: mu_a(X + c_a), or the bounce-back transpose
+                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
+                unsigned src = own;
+                bool solid = false;
+                if (c0 != 0) { src += bxo[1 + c0]; solid = solid || (c0 < 0 ? xm < 0 : xp < 0); }
+                if (DIM == 3 && c1 != 0) { src += byo[1 + c1]; solid = solid || (c1 < 0 ? ym < 0 : yp < 0); }
+                if (cm != 0) { src += bmo[1 + cm]; solid = solid || (cm < 0 ? mmv < 0 : mpv < 0); }
+                const int lo = a < La::opp(a) ? a : La::opp(a);
+                const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
+                                          : src + (unsigned)((a - lo) * M.pb);
+                lf_[a] = ldb(M, lo, sg);
+            }
+        } else {
 #pragma unroll
             for (int a = 1; a < Q; ++a) {
                 const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
-                float v;
-                if (s == 0) {
-                    // reversed shift: mu_a(X + c_a), or bounce-back transpose
-                    unsigned src = own;
-                    bool solid = false;
-                    if (c0 != 0) { src += bx[1 + c0]; solid = solid || (c0 < 0 ? xm < 0 : xp < 0); }
-                    if (DIM == 3 && c1 != 0) { src += by[1 + c1]; solid = solid || (c1 < 0 ? ym < 0 : yp < 0); }
-                    if (cm != 0) { src += bm[1 + cm]; solid = solid || (cm < 0 ? mmv < 0 : mpv < 0); }
-                    const int lo = a < La::opp(a) ? a : La::opp(a);
-                    const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
-                                              : src + (unsigned)((a - lo) * M.pb);
-                    v = ldb(M, s * Q + lo, sg);
-                } else {
-                    // weights of the reversed velocity: offsets k' with Lambda_k'(-e)
-                    const W3 wxw = wsel(-c0, L), wyw = wsel(-c1, L), wmw = wsel(-cm, L);
-                    const float wxv[3] = {wxw.m, wxw.z, wxw.p};
-                    const float wyv[3] = {wyw.m, wyw.z, wyw.p};
-                    const float wmv[3] = {wmw.m, wmw.z, wmw.p};
-                    v = 0.0f;
+                // weights of the reversed velocity: offsets k' with Lambda_k'(-e)
+                const W3 wxw = wsel(-c0, L), wyw = wsel(-c1, L), wmw = wsel(-cm, L);
+                const float wxv[3] = {wxw.m, wxw.z, wxw.p};
+                const float wyv[3] = {wyw.m, wyw.z, wyw.p};
+                const float wmv[3] = {wmw.m, wmw.z, wmw.p};
+                float v = 0.0f;
 #pragma unroll
-                    for (int km = -1; km <= 1; ++km) {
-                        if (cm == 0 && km != 0) continue;
-                        float vy = 0.0f;
+                for (int km = -1; km <= 1; ++km) {
+                    if (cm == 0 && km != 0) continue;
+                    float vy = 0.0f;
 #pragma unroll
-                        for (int ky = -1; ky <= 1; ++ky) {
-                            if ((DIM == 2 || c1 == 0) && ky != 0) continue;
-                            float vx = 0.0f;
+                    for (int ky = -1; ky <= 1; ++ky) {
+                        if ((DIM == 2 || c1 == 0) && ky != 0) continue;
+                        float vx = 0.0f;
 #pragma unroll
-                            for (int kx = -1; kx <= 1; ++kx) {
-                                if (c0 == 0 && kx != 0) continue;
-                                const unsigned off = own + bm[1 + km] + by[1 + ky] + bx[1 + kx];
-                                vx = fmaf(wxv[1 + kx], ldb(M, s * Q + a, off), vx);
-                            }
-                            vy = fmaf(wyv[1 + ky], vx, vy);
+                        for (int kx = -1; kx <= 1; ++kx) {
+                            if (c0 == 0 && kx != 0) continue;
+                            const unsigned off = own + bmo[1 + km] + byo[1 + ky] + bxo[1 + kx];
+                            vx = fmaf(wxv[1 + kx], ldb(M, pb0 + a, off), vx);
                         }
-                        v = fmaf(wmv[1 + km], vy, v);
+                        vy = fmaf(wyv[1 + ky], vx, vy);
                     }
-                    // transposed walls
-                    if (side != 0) {
-                        const int ca = Fr::comp(a, axis);
-                        if (ca != 0) {
-                            if (side * ca < 0) v = fmaf(L[2], ldb(M, s * Q + a, own), v);
-                            else v = fmaf(L[0], ldb(M, s * Q + La::opp(a), own), v);
-                        }
+                    v = fmaf(wmv[1 + km], vy, v);
+                }
+                // transposed walls
+                if (side != 0) {
+                    const int ca = Fr::comp(a, axis);
+                    if (ca != 0) {
+                        if (side * ca < 0) v = fmaf(L[2], ldb(M, pb0 + a, own), v);
+                        else v = fmaf(L[0], ldb(M, pb0 + La::opp(a), own), v);
                     }
                 }
                 lf_[a] = v;
             }
-            float lp0 = lf_[0];
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                lp0 = fmaf(La::wr(a), lf_[a], lp0);
-                stb(O, s * Q + a, own, lf_[a]);
-            }
-            stb(O, s * Q, own, lp0);
         }
+        float lp0 = lf_[0];
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            lp0 = fmaf(La::wr(a), lf_[a], lp0);
+            stb(O, pb0 + a, own, lf_[a]);
+        }
+        stb(O, pb0, own, lp0);
     }
 }
 
@@ -355,8 +444,9 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const LatParams* __restrict
 // ---------------------------------------------------------------- launchers
 template <int LAT, int NS>
 static hipError_t adj_t(const Launch& L, const float* lam_in, float* mu, double* gpart) {
-    hipLaunchKernelGGL((k_adj_collide<LAT, NS>), dim3(L.ntiles), dim3(L.bx, L.by), 0, L.stream,
-                       L.src, lam_in, mu, L.lp, L.tiles, gpart);
+    if (L.bx * L.by != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adj_collide<LAT, NS>), dim3(L.ntiles), dim3(64, NS), 0, L.stream,
+                       L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
     return hipGetLastError();
 }
 
@@ -376,8 +466,9 @@ hipError_t launch_adjoint(int lattice, int ns, const Launch& L, const float* lam
 
 template <int LAT, int NS>
 static hipError_t adjs_t(const Launch& L, const float* mu, float* lam_out) {
-    hipLaunchKernelGGL((k_adj_stream<LAT, NS>), dim3(L.ntiles), dim3(L.bx, L.by), 0, L.stream, mu,
-                       lam_out, L.lp, L.tiles);
+    if (L.bx * L.by != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adj_stream<LAT, NS>), dim3(L.ntiles), dim3(64, NS), 0, L.stream, mu,
+                       lam_out, L.lp, L.tiles, L.bx);
     return hipGetLastError();
 }
 

@@ -69,186 +69,242 @@ __device__ __forceinline__ void tau_vjp(const float (&rho)[NS], float R, float n
     }
 }
 
-// Vector-Jacobian product of the collision at one node, in population space.
-// In: the species densities rho and momenta jm = sum_a c_a f_a (integer
-// directions) of the streamed populations f; lt = dL/df~.  Out: lt = dL/df;
-// dL/dK_ij and dL/dg accumulated.  Exact math of the forward collision,
-// evaluated directly in FP32 (the adjoint is a linearisation: its error
-// enters the gradient, not the state).
-template <int LAT, int NS>
-__device__ __forceinline__ void collide_vjp(const float (&rho)[NS], const float (&jm)[NS][3],
-                                            float (&lt)[NS][Lat<LAT>::Q], const CollConst& C,
-                                            float (&dK)[NS][NS], float (&dg)[3]) {
-    constexpr int Q = Lat<LAT>::Q;
-    using L = Lat<LAT>;
-    // ---------------------------------------------------- forward recomputation
+// Reverse mode of the collision at one node, in population space, in pieces
+// shared by the one-thread-per-node form (collide_vjp) and the
+// one-wave-per-species form of the reverse step.  Exact math of the forward
+// collision, evaluated directly in FP32 (the adjoint is a linearisation: its
+// error enters the gradient, not the state).
+
+// Forward recomputation from the species densities rho and momenta
+// jm = sum_a c_a f_a (integer directions) of the streamed populations.
+template <int NS>
+struct VjpFwd {
     float ue[NS][3];
     bool live[NS];
+    float R, n, iR, U[3], UU;
+    float y[NS][NS];
+};
+
+template <int NS>
+__device__ __forceinline__ void vjp_forward(const float (&rho)[NS], const float (&jm)[NS][3],
+                                            const CollConst& C, VjpFwd<NS>& f) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        live[s] = fabsf(rho[s]) > kRhoTiny;
-        const float cr = live[s] ? C.c[s] / rho[s] : 0.0f;
+        f.live[s] = fabsf(rho[s]) > kRhoTiny;
+        const float cr = f.live[s] ? C.c[s] / rho[s] : 0.0f;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ue[s][d] = fmaf(jm[s][d], cr, 0.5f * C.g[d]);
+        for (int d = 0; d < 3; ++d) f.ue[s][d] = fmaf(jm[s][d], cr, 0.5f * C.g[d]);
     }
-    float R = 0.0f, n = 0.0f;
+    f.R = 0.0f;
+    f.n = 0.0f;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        R += rho[s];
-        n += rho[s] * C.invM[s];
+        f.R += rho[s];
+        f.n += rho[s] * C.invM[s];
     }
-    const float iR = 1.0f / R;
-    float U[3] = {0.0f, 0.0f, 0.0f};
+    f.iR = 1.0f / f.R;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f.U[d] = 0.0f;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) U[d] += rho[s] * ue[s][d] * iR;
-    float y[NS][NS];
-    tau_solve<NS>(rho, R, n, C, y);
-    float V[NS][3];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) V[i][d] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if (j == i) continue;
-            const float w = rho[j] * y[i][j] * iR;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) V[i][d] += w * (ue[i][d] - ue[j][d]);
-        }
-    }
-    const float UU = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+        for (int d = 0; d < 3; ++d) f.U[d] += rho[s] * f.ue[s][d] * f.iR;
+    tau_solve<NS>(rho, f.R, f.n, C, f.y);
+    f.UU = f.U[0] * f.U[0] + f.U[1] * f.U[1] + f.U[2] * f.U[2];
+}
 
-    // ------------------------------------------------------------------ reverse
-    float dU[3] = {0.0f, 0.0f, 0.0f}, dR = 0.0f, dn = 0.0f;
-    float drho[NS], due[NS][3], dY[NS][NS];
+// Adjoints of the shared intermediates: u, rho, the species densities and
+// equilibrium velocities, and y (dY[i][j] from species i's friction).
+template <int NS>
+struct VjpAcc {
+    float dU[3], dR;
+    float drho[NS], due[NS][3];
+    float dY[NS][NS];
+};
+
+template <int NS>
+__device__ __forceinline__ void vjp_zero(VjpAcc<NS>& A) {
+    A.dU[0] = A.dU[1] = A.dU[2] = 0.0f;
+    A.dR = 0.0f;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        drho[s] = 0.0f;
-        due[s][0] = due[s][1] = due[s][2] = 0.0f;
+        A.drho[s] = 0.0f;
+        A.due[s][0] = A.due[s][1] = A.due[s][2] = 0.0f;
 #pragma unroll
-        for (int t = 0; t < NS; ++t) dY[s][t] = 0.0f;
+        for (int t = 0; t < NS; ++t) A.dY[s][t] = 0.0f;
+    }
+}
+
+// Species i's part (i a compile-time index): lt = dL/df~_i on entry, the
+// direct term (1 - 1/tau_i) dL/df~_i on return; its terms added to A and
+// rho_i dL/dF_i . (dF/dg) to dg.
+template <int LAT, int NS>
+__device__ __forceinline__ void vjp_species(int i, const float (&rho)[NS], const VjpFwd<NS>& f,
+                                            const CollConst& C, float (&lt)[Lat<LAT>::Q],
+                                            VjpAcc<NS>& A, float (&dg)[3]) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+    const float c = C.c[i], ics = C.inv_cs2[i], itau = C.inv_tau[i], fp = C.fpref[i];
+    const float iR = f.iR;
+    // friction V_i = sum_j W_ij (ue_i - ue_j), W_ij = rho_j y_ij / R
+    float V[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        if (j == i) continue;
+        const float w = rho[j] * f.y[i][j] * iR;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[d] += w * (f.ue[i][d] - f.ue[j][d]);
+    }
+    float du[3], Fv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        du[d] = f.ue[i][d] - f.U[d];
+        Fv[d] = rho[i] * C.g[d];
+    }
+    const float* U = f.U;
+    const float uD = U[0] * du[0] + U[1] * du[1] + U[2] * du[2];
+    const float uV = U[0] * V[0] + U[1] * V[1] + U[2] * V[2];
+    float gU[3] = {0, 0, 0}, gdu[3] = {0, 0, 0}, gV[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
+    float s_uD = 0.0f, s_uV = 0.0f, s_uF = 0.0f, s_UU = 0.0f, drf = 0.0f;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const float ex = c * L::cx(a), ey = c * L::cy(a), ez = c * L::cz(a);
+        const float w = L::w(a);
+        const float eU = ex * U[0] + ey * U[1] + ez * U[2];
+        const float eD = ex * du[0] + ey * du[1] + ez * du[2];
+        const float eV = ex * V[0] + ey * V[1] + ez * V[2];
+        const float eF = ex * Fv[0] + ey * Fv[1] + ez * Fv[2];
+        const float P = 1.0f + ics * eU + 0.5f * ics * ics * eU * eU - 0.5f * ics * f.UU;
+        const float feq = w * rho[i] * P;
+        const float lam = lt[a];
+        lt[a] = (1.0f - itau) * lam;
+        const float df0 = itau * lam;
+        const float dfeq = df0 * (1.0f + ics * (eD - uD)) - lam * ics * (eV - uV);
+        const float deD = df0 * feq * ics;
+        const float deV = -lam * feq * ics;
+        const float dS = fp * lam;
+        const float deF = dS * w * ics * (1.0f + ics * eU);
+        float deU = dS * w * ics * ics * eF;
+        drf += dfeq * w * P;
+        const float dP = dfeq * w * rho[i];
+        deU += dP * (ics + ics * ics * eU);
+        s_UU += -0.5f * ics * dP;
+        s_uD -= deD;
+        s_uV -= deV;
+        s_uF -= dS * w * ics;
+        gU[0] += deU * ex; gU[1] += deU * ey; gU[2] += deU * ez;
+        gdu[0] += deD * ex; gdu[1] += deD * ey; gdu[2] += deD * ez;
+        gV[0] += deV * ex; gV[1] += deV * ey; gV[2] += deV * ez;
+        gF[0] += deF * ex; gF[1] += deF * ey; gF[2] += deF * ez;
     }
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        const float c = C.c[i], ics = C.inv_cs2[i], itau = C.inv_tau[i], fp = C.fpref[i];
-        float du[3], Fv[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            du[d] = ue[i][d] - U[d];
-            Fv[d] = rho[i] * C.g[d];
-        }
-        const float uD = U[0] * du[0] + U[1] * du[1] + U[2] * du[2];
-        const float uV = U[0] * V[i][0] + U[1] * V[i][1] + U[2] * V[i][2];
-        float gU[3] = {0, 0, 0}, gdu[3] = {0, 0, 0}, gV[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
-        float s_uD = 0.0f, s_uV = 0.0f, s_uF = 0.0f, s_UU = 0.0f, drf = 0.0f;
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const float ex = c * L::cx(a), ey = c * L::cy(a), ez = c * L::cz(a);
-            const float w = L::w(a);
-            const float eU = ex * U[0] + ey * U[1] + ez * U[2];
-            const float eD = ex * du[0] + ey * du[1] + ez * du[2];
-            const float eV = ex * V[i][0] + ey * V[i][1] + ez * V[i][2];
-            const float eF = ex * Fv[0] + ey * Fv[1] + ez * Fv[2];
-            const float P = 1.0f + ics * eU + 0.5f * ics * ics * eU * eU - 0.5f * ics * UU;
-            const float feq = w * rho[i] * P;
-            const float lam = lt[i][a];
-            lt[i][a] = (1.0f - itau) * lam;
-            const float df0 = itau * lam;
-            const float dfeq = df0 * (1.0f + ics * (eD - uD)) - lam * ics * (eV - uV);
-            const float deD = df0 * feq * ics;
-            const float deV = -lam * feq * ics;
-            const float dS = fp * lam;
-            const float deF = dS * w * ics * (1.0f + ics * eU);
-            float deU = dS * w * ics * ics * eF;
-            drf += dfeq * w * P;
-            const float dP = dfeq * w * rho[i];
-            deU += dP * (ics + ics * ics * eU);
-            s_UU += -0.5f * ics * dP;
-            s_uD -= deD;
-            s_uV -= deV;
-            s_uF -= dS * w * ics;
-            gU[0] += deU * ex; gU[1] += deU * ey; gU[2] += deU * ez;
-            gdu[0] += deD * ex; gdu[1] += deD * ey; gdu[2] += deD * ez;
-            gV[0] += deV * ex; gV[1] += deV * ey; gV[2] += deV * ez;
-            gF[0] += deF * ex; gF[1] += deF * ey; gF[2] += deF * ez;
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            gU[d] += s_uD * du[d] + s_uV * V[i][d] + s_uF * Fv[d] + 2.0f * s_UU * U[d];
-            gdu[d] += s_uD * U[d];
-            gV[d] += s_uV * U[d];
-            gF[d] += s_uF * U[d];
-        }
-        drho[i] += drf;
-        // F_i = rho_i g
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            drho[i] += gF[d] * C.g[d];
-            dg[d] += rho[i] * gF[d];
-        }
-        // du_i = ue_i - U
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            due[i][d] += gdu[d];
-            dU[d] += gU[d] - gdu[d];
-        }
-        // V_i = sum_j W_ij (ue_i - ue_j), W_ij = rho_j y_ij / R
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if (j == i) continue;
-            const float W = rho[j] * y[i][j] * iR;
-            float dW = 0.0f;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                dW += gV[d] * (ue[i][d] - ue[j][d]);
-                due[i][d] += W * gV[d];
-                due[j][d] -= W * gV[d];
-            }
-            drho[j] += dW * y[i][j] * iR;
-            dY[i][j] += dW * rho[j] * iR;
-            dR -= dW * W * iR;
-        }
+    for (int d = 0; d < 3; ++d) {
+        gU[d] += s_uD * du[d] + s_uV * V[d] + s_uF * Fv[d] + 2.0f * s_UU * U[d];
+        gdu[d] += s_uD * U[d];
+        gV[d] += s_uV * U[d];
+        gF[d] += s_uF * U[d];
     }
+    A.drho[i] += drf;
+    // F_i = rho_i g
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A.drho[i] += gF[d] * C.g[d];
+        dg[d] += rho[i] * gF[d];
+    }
+    // du_i = ue_i - U
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A.due[i][d] += gdu[d];
+        A.dU[d] += gU[d] - gdu[d];
+    }
+    // V_i = sum_j W_ij (ue_i - ue_j)
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        if (j == i) continue;
+        const float W = rho[j] * f.y[i][j] * iR;
+        float dW = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            dW += gV[d] * (f.ue[i][d] - f.ue[j][d]);
+            A.due[i][d] += W * gV[d];
+            A.due[j][d] -= W * gV[d];
+        }
+        A.drho[j] += dW * f.y[i][j] * iR;
+        A.dY[i][j] += dW * rho[j] * iR;
+        A.dR -= dW * W * iR;
+    }
+}
+
+// Reverse of the mixture velocity, of the cross-relaxation solve and of
+// rho = sum rho_s, n = sum rho_s/M_s: completes A.drho and A.due, adds dL/dK.
+template <int NS>
+__device__ __forceinline__ void vjp_mixture(const float (&rho)[NS], const VjpFwd<NS>& f,
+                                            const CollConst& C, VjpAcc<NS>& A,
+                                            float (&dK)[NS][NS]) {
+    const float iR = f.iR;
     // U = sum_s rho_s ue_s / R
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            due[s][d] += dU[d] * rho[s] * iR;
-            drho[s] += dU[d] * ue[s][d] * iR;
+            A.due[s][d] += A.dU[d] * rho[s] * iR;
+            A.drho[s] += A.dU[d] * f.ue[s][d] * iR;
         }
-    dR -= (dU[0] * U[0] + dU[1] * U[1] + dU[2] * U[2]) * iR;
+    float dR = A.dR - (A.dU[0] * f.U[0] + A.dU[1] * f.U[1] + A.dU[2] * f.U[2]) * iR;
     // y: both orders of a pair are the same unknown
     float dYs[NS][NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i)
 #pragma unroll
-        for (int j = 0; j < NS; ++j) dYs[i][j] = i < j ? dY[i][j] + dY[j][i] : 0.0f;
-    tau_vjp<NS>(rho, R, n, C, dYs, drho, dR, dn, dK);
+        for (int j = 0; j < NS; ++j) dYs[i][j] = i < j ? A.dY[i][j] + A.dY[j][i] : 0.0f;
+    float dn = 0.0f;
+    tau_vjp<NS>(rho, f.R, f.n, C, dYs, A.drho, dR, dn, dK);
     // R = sum rho, n = sum rho/M
 #pragma unroll
-    for (int s = 0; s < NS; ++s) drho[s] += dR + dn * C.invM[s];
-    // ue_s = j_s/rho_s + g/2, j_s = c_s sum_a c_a f
-    float dj[NS][3];
+    for (int s = 0; s < NS; ++s) A.drho[s] += dR + dn * C.invM[s];
+}
+
+// Species s's last part (s compile-time): reverse of ue_s = c_s j_s/rho_s +
+// g/2 and of rho_s = sum_a f_a, j_s = sum_a c_a f_a: lt += drho_s + c_s
+// c_a . dj_s; dg += due_s/2.
+template <int LAT, int NS>
+__device__ __forceinline__ void vjp_finish(int s, const float (&rho)[NS], const VjpFwd<NS>& f,
+                                           const CollConst& C, const VjpAcc<NS>& A,
+                                           float (&lt)[Lat<LAT>::Q], float (&dg)[3]) {
+    constexpr int Q = Lat<LAT>::Q;
+    using L = Lat<LAT>;
+    float dj[3];
+    float drho = A.drho[s];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            dg[d] += 0.5f * due[s][d];
-            if (live[s]) {
-                dj[s][d] = due[s][d] / rho[s];
-                drho[s] -= due[s][d] * (ue[s][d] - 0.5f * C.g[d]) / rho[s];
-            } else {
-                dj[s][d] = 0.0f;
-            }
+    for (int d = 0; d < 3; ++d) {
+        dg[d] += 0.5f * A.due[s][d];
+        if (f.live[s]) {
+            dj[d] = A.due[s][d] / rho[s];
+            drho -= A.due[s][d] * (f.ue[s][d] - 0.5f * C.g[d]) / rho[s];
+        } else {
+            dj[d] = 0.0f;
         }
-#pragma unroll
-        for (int a = 0; a < Q; ++a)
-            lt[s][a] += drho[s] + C.c[s] * (L::cx(a) * dj[s][0] + L::cy(a) * dj[s][1] +
-                                             L::cz(a) * dj[s][2]);
     }
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+        lt[a] += drho + C.c[s] * (L::cx(a) * dj[0] + L::cy(a) * dj[1] + L::cz(a) * dj[2]);
+}
+
+// Vector-Jacobian product of the collision at one node, all species:
+// lt = dL/df~ on entry, dL/df on return; dL/dK_ij and dL/dg accumulated.
+template <int LAT, int NS>
+__device__ __forceinline__ void collide_vjp(const float (&rho)[NS], const float (&jm)[NS][3],
+                                            float (&lt)[NS][Lat<LAT>::Q], const CollConst& C,
+                                            float (&dK)[NS][NS], float (&dg)[3]) {
+    VjpFwd<NS> f;
+    vjp_forward<NS>(rho, jm, C, f);
+    VjpAcc<NS> A;
+    vjp_zero<NS>(A);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) vjp_species<LAT, NS>(i, rho, f, C, lt[i], A, dg);
+    vjp_mixture<NS>(rho, f, C, A, dK);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) vjp_finish<LAT, NS>(s, rho, f, C, A, lt[s], dg);
 }
 
 }  // namespace lbmmc

@@ -363,6 +363,17 @@ struct lbm_mc_ctx {
     // the initialisation VJP of single-lattice contexts)
     float* dmu = nullptr;
     float* dlam = nullptr;
+    Tile* adj_tiles = nullptr;          // the reverse step's own tile list
+    // captured launch sequences of lbm_mc_replay / lbm_mc_adjoint_run, keyed
+    // by their arguments
+    struct SeqGraph {
+        int kind;
+        const void *a, *b, *c;
+        int64_t n, stride;
+        hipGraphExec_t exec;
+    };
+    std::vector<SeqGraph> seq_graphs;
+    int adj_ntiles = 0, adj_bx = 64, adj_by = 1;
     double* dgpart = nullptr;
     size_t dgpart_cap = 0;
     double* dx0 = nullptr;
@@ -375,6 +386,41 @@ void drop_graphs(lbm_mc_ctx* c) {
         if (g) hipGraphExecDestroy(g);
         g = nullptr;
     }
+    for (auto& g : c->seq_graphs) hipGraphExecDestroy(g.exec);
+    c->seq_graphs.clear();
+}
+
+// Run a launch sequence through a captured graph, capturing it on first use
+// for this argument set (at most 8 kept).  issue(stream) enqueues the
+// kernels; it must not record memsets.
+template <class Issue>
+lbm_mc_status run_sequence(lbm_mc_ctx* c, int kind, const void* a, const void* b, const void* d,
+                           int64_t n, int64_t stride, Issue&& issue) {
+    for (auto& g : c->seq_graphs)
+        if (g.kind == kind && g.a == a && g.b == b && g.c == d && g.n == n && g.stride == stride) {
+            HIPCHECK(hipGraphLaunch(g.exec, c->stream));
+            return LBM_MC_OK;
+        }
+    if (c->seq_graphs.size() >= 8) {
+        for (auto& g : c->seq_graphs) hipGraphExecDestroy(g.exec);
+        c->seq_graphs.clear();
+    }
+    HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    lbm_mc_status st = issue(c->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (st != LBM_MC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    c->seq_graphs.push_back({kind, a, b, d, n, stride, exec});
+    HIPCHECK(hipGraphLaunch(exec, c->stream));
+    return LBM_MC_OK;
 }
 
 lbm_mc_status build_tiles(lbm_mc_ctx* c) {
@@ -423,10 +469,10 @@ lbm_mc_status build_tiles(lbm_mc_ctx* c) {
     return LBM_MC_OK;
 }
 
-// Default execution shape: the widest work-group (fewest partial tiles) that
-// still gives at least two column blocks per compute unit, then as many layers
-// per thread as keep about eight tiles per compute unit (long marches reuse the
-// three-layer register stencil; short ones fill the chip on small lattices).
+// Default execution shape: 64-column tiles, one wave per species, with as
+// many layers per tile as keep about eight tiles per compute unit (long
+// marches reuse the three-layer register stencil; short ones fill the chip on
+// small lattices).
 Tuning default_tuning(const lbm_mc_params* p, int n_lattices, int dim, int cus) {
     auto columns = [&](int bx, int by) {
         int64_t n = 0;
@@ -440,19 +486,13 @@ Tuning default_tuning(const lbm_mc_params* p, int n_lattices, int dim, int cus) 
         for (int l = 0; l < n_lattices; ++l) m = std::max<int64_t>(m, dim == 3 ? p[l].nz : p[l].ny);
         return m;
     };
+    // the species-split variant over 64-column rows: as fast as or faster
+    // than one thread per column on every workload measured (it keeps several
+    // times more waves per SIMD)
     Tuning t;
-    if (dim == 3) {
-        t.bx = 64; t.by = 4;
-    } else {
-        t.by = 1;
-        t.bx = 64;
-        for (int bx : {256, 128}) {
-            if (columns(bx, 1) * layers() >= 2 * (int64_t)cus) {
-                t.bx = bx;
-                break;
-            }
-        }
-    }
+    t.bx = 64;
+    t.by = 1;
+    t.split = 1;
     const int64_t cols = columns(t.bx, t.by);
     int64_t rows = cols * layers() / (8 * (int64_t)cus);
     t.rows = (int)std::max<int64_t>(1, std::min<int64_t>(dim == 3 ? 16 : 32, rows));
@@ -536,6 +576,38 @@ lbm_mc_status check_flag(lbm_mc_ctx* c) {
     return LBM_MC_OK;
 }
 
+// Tiles of the reverse step: 64 columns (64 x 1 in 2-D, 32 x 2 in 3-D, one
+// wave per species), layers per tile chosen for about eight tiles per
+// compute unit.
+lbm_mc_status build_adj_tiles(lbm_mc_ctx* c) {
+    const auto& q = c->params[0];
+    const int bx = c->DIM == 3 ? 32 : 64, by = c->DIM == 3 ? 2 : 1;
+    const int nm = c->DIM == 2 ? q.ny : q.nz;
+    const int nxb = (q.nx + bx - 1) / bx, nyb = c->DIM == 3 ? (q.ny + by - 1) / by : 1;
+    const int64_t cols = (int64_t)nxb * nyb;
+    const int rows = (int)std::max<int64_t>(1, std::min<int64_t>(16, cols * nm / (8 * (int64_t)c->cus)));
+    std::vector<Tile> h;
+    for (int xb = 0; xb < nxb; ++xb)
+        for (int yb = 0; yb < nyb; ++yb)
+            for (int m0 = 0; m0 < nm; m0 += rows) {
+                Tile t{};
+                t.lat = 0;
+                t.x0 = xb * bx;
+                t.y0 = yb * by;
+                t.m0 = m0;
+                t.m1 = std::min(nm, m0 + rows);
+                h.push_back(t);
+            }
+    HIPCHECK(hipMalloc(&c->adj_tiles, h.size() * sizeof(Tile)));
+    HIPCHECK(hipMemcpyAsync(c->adj_tiles, h.data(), h.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                            c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    c->adj_ntiles = (int)h.size();
+    c->adj_bx = bx;
+    c->adj_by = by;
+    return LBM_MC_OK;
+}
+
 lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (c->L != 1) return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: batched contexts are not supported");
@@ -544,8 +616,12 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
         HIPCHECK(hipMemsetAsync(c->dmu, 0, bytes, c->stream));
     }
+    if (!c->adj_tiles) {
+        lbm_mc_status st = build_adj_tiles(c);
+        if (st != LBM_MC_OK) return st;
+    }
     const size_t ng = (size_t)(c->N * (c->N - 1) / 2 + 3);
-    const size_t need = ng * std::max(c->htiles.size(), (size_t)init_blocks(c));
+    const size_t need = ng * std::max((size_t)c->adj_ntiles, (size_t)init_blocks(c));
     if (need > c->dgpart_cap) {
         if (c->dgpart) hipFree(c->dgpart);
         c->dgpart = nullptr;
@@ -582,10 +658,13 @@ lbm_mc_status grad_sum(lbm_mc_ctx* c, int nblocks, double* grad) {
 
 // kernel A (partials accumulated per tile), kernel B
 lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in,
-                          float* lam_out) {
+                          float* lam_out, hipStream_t stream) {
     const int ng = c->N * (c->N - 1) / 2 + 3;
-    Launch L = make_launch(c, f_prev, nullptr, c->stream);
-    L.grid = L.ntiles;
+    Launch L = make_launch(c, f_prev, nullptr, stream);
+    L.tiles = c->adj_tiles;
+    L.ntiles = L.grid = c->adj_ntiles;
+    L.bx = c->adj_bx;
+    L.by = c->adj_by;
     HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, c->dmu, c->dgpart, ng));
     HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, c->dmu, lam_out));
     return LBM_MC_OK;
@@ -825,6 +904,7 @@ lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* c, int32_t bx, int32_t by, int32_t r
     if (rows) t.rows = rows;
     if (persistent >= 0) t.persistent = persistent;
     if (variant >= 0) t.split = variant;
+    else if (t.bx * t.by != 64) t.split = 0;   // keep the variant if the shape allows it
     if (t.split != 0 && t.split != 1) return fail(LBM_MC_ERR_INVALID, "variant must be 0 or 1");
     if (t.bx < 8 || t.bx > 256 || t.bx % 8) return fail(LBM_MC_ERR_INVALID, "block_x must be 8..256, multiple of 8");
     if (c->DIM == 2 && t.by != 1) return fail(LBM_MC_ERR_INVALID, "block_y must be 1 in 2-D");
@@ -956,6 +1036,7 @@ lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
     hipFree(c->dgpart);
     hipFree(c->dlam);
     hipFree(c->dx0);
+    hipFree(c->adj_tiles);
     delete c;
     return LBM_MC_OK;
 }
@@ -968,9 +1049,9 @@ lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* c, const float* f_prev, const floa
         return fail(LBM_MC_ERR_INVALID, "adjoint_step: NULL buffer");
     if (lam_out == lam_in || lam_out == f_prev)
         return fail(LBM_MC_ERR_INVALID, "adjoint_step: lam_out must not alias lam_in or f_prev");
-    const int nt = (int)c->htiles.size();
+    const int nt = c->adj_ntiles;
     st = grad_clear(c, nt);
-    if (st == LBM_MC_OK) st = adjoint_one(c, f_prev, lam_in, lam_out);
+    if (st == LBM_MC_OK) st = adjoint_one(c, f_prev, lam_in, lam_out, c->stream);
     if (st == LBM_MC_OK) st = grad_sum(c, nt, grad);
     return st;
 }
@@ -994,15 +1075,20 @@ lbm_mc_status lbm_mc_replay(lbm_mc_ctx* c, const float* src, int64_t n, float* s
     if (n < 0) return fail(LBM_MC_ERR_INVALID, "replay: n must be >= 0");
     lbm_mc_status st = check_sequence(c, states, n, stride);
     if (st != LBM_MC_OK) return st;
-    const float* s = src;
-    for (int64_t k = 0; k < n; ++k) {
-        float* d = states + k * stride;
-        if (d == s) return fail(LBM_MC_ERR_INVALID, "replay: src is slot %lld", (long long)k);
-        st = launch_one(c, s, d, c->stream);
-        if (st != LBM_MC_OK) return st;
-        s = d;
-    }
-    return LBM_MC_OK;
+    for (int64_t k = 0; k < n; ++k)
+        if (states + k * stride == src)
+            return fail(LBM_MC_ERR_INVALID, "replay: src is slot %lld", (long long)k);
+    if (n == 0) return LBM_MC_OK;
+    return run_sequence(c, 0, src, states, nullptr, n, stride, [&](hipStream_t strm) {
+        const float* s = src;
+        for (int64_t k = 0; k < n; ++k) {
+            float* d = states + k * stride;
+            lbm_mc_status r = launch_one(c, s, d, strm);
+            if (r != LBM_MC_OK) return r;
+            s = d;
+        }
+        return LBM_MC_OK;
+    });
 }
 
 lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t stride, int64_t n,
@@ -1021,16 +1107,20 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t str
     }
     // step k (1..n) reverses the step from states[n-k] and writes lam_out when
     // n-k is even, the context's buffer otherwise, so the last lands in lam_out
-    const int nt = (int)c->htiles.size();
+    const int nt = c->adj_ntiles;
     st = grad_clear(c, nt);
     if (st != LBM_MC_OK) return st;
-    const float* src = lam_in;
-    for (int64_t k = 1; k <= n; ++k) {
-        float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
-        st = adjoint_one(c, states + (n - k) * stride, src, dst);
-        if (st != LBM_MC_OK) return st;
-        src = dst;
-    }
+    st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
+        const float* src = lam_in;
+        for (int64_t k = 1; k <= n; ++k) {
+            float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
+            lbm_mc_status r = adjoint_one(c, states + (n - k) * stride, src, dst, strm);
+            if (r != LBM_MC_OK) return r;
+            src = dst;
+        }
+        return LBM_MC_OK;
+    });
+    if (st != LBM_MC_OK) return st;
     return grad_sum(c, nt, grad);
 }
 

@@ -43,7 +43,7 @@ def _gpu_run(w, steps, tuning=None, x0=None):
     x0 = w.x0() if x0 is None else x0
     sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
     if tuning:
-        sim.set_tuning(*tuning)
+        sim.set_tuning(*(tuple(tuning) + (0,) * (5 - len(tuning))))   # variant 0 unless given
     m0 = sim.moments(fields=False)["mass"][0].copy()
     sim.step(steps)
     out = sim.moments()
