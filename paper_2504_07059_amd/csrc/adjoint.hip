@@ -46,20 +46,6 @@ __device__ __forceinline__ void block_reduce_add(double (&acc)[NG], double* __re
     }
 }
 
-// Column of a work-group's 64 lanes: x fastest over bx columns, then y (3-D).
-// Lanes beyond the lattice follow a valid column and do not store.
-template <int LAT>
-__device__ __forceinline__ bool tile_column(const Tile& T, const LatParams& P, int lane, int bx,
-                                            int& x, int& y) {
-    constexpr int DIM = Lat<LAT>::DIM;
-    x = T.x0 + (DIM == 3 ? lane % bx : lane);
-    y = DIM == 3 ? T.y0 + lane / bx : 0;
-    const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
-    x = x < P.nx ? x : P.nx - 1;
-    if (DIM == 3) y = y < P.ny ? y : P.ny - 1;
-    return inside;
-}
-
 // ------------------------------------------------------------------ kernel A
 // One wave per species over 64 columns.  Per layer: the wave gathers f(t) of
 // its species from f~(t-1) and publishes its density and momentum in LDS;
@@ -203,7 +189,8 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
     int x, y;
-    const bool inside = tile_column<LAT>(T, P, lane, bx, x, y);
+    bool zero;
+    const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
     const int64_t lf = P.plane * NS * Q;
     Op op{make_buf(lam + P.base, lf, P.plane), make_buf(mu + P.base, lf, P.plane),
           coll_const(P), x1, x2, s, lane, inside, {}};
@@ -211,7 +198,8 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
     for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-    march1<LAT>(make_buf(fprev + P.base, lf, P.plane), G, s, L, x, y, T.m0, T.m1, op);
+    march1<LAT>(make_buf(fprev + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
+                T.m1, op);
     block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
@@ -236,7 +224,8 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
     int x, y;
-    if (!tile_column<LAT>(T, P, lane, bx, x, y)) return;
+    bool zero;
+    if (!tile_column<LAT>(T, P, lane, bx, x, y, zero)) return;
     const GatherConst G = gather_const(P, DIM);
     const int64_t lf = P.plane * NS * Q;
     const Buf M = make_buf(mu + P.base, lf, P.plane);

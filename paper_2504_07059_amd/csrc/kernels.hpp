@@ -102,31 +102,76 @@ struct Col {
     bool sxm, sxp, sym, syp;
 };
 
+// Cross-lane moves along a wave: lane i takes lane i-1's (from_left) or lane
+// i+1's (from_right) value; the lane with no such neighbour takes `old`.
+__device__ __forceinline__ float from_left(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+
+// How the gather reads a plane value and its x neighbours at a row.
+// NbLoad: every value by its own load (any work-group shape).
+struct NbLoad {
+    static constexpr bool wave = false;
+    __device__ __forceinline__ void trip(const Buf& b, int p, unsigned row, const Col& c,
+                                         float& m, float& z, float& q) const {
+        z = ldb(b, p, row);
+        m = ldb(b, p, row + c.bxm);
+        q = ldb(b, p, row + c.bxp);
+    }
+};
+
+// NbWave: the 64 lanes of the wave hold the 64 consecutive columns of one row.
+// A plane row is read once and the x neighbours are taken from the adjacent
+// lanes; one more load, in which lane 0 reads the column before the row
+// segment and lane 63 the one after it (the other lanes re-read their own
+// value: the same cache line), supplies the two values beyond the wave's ends.
+// Walls and periodicity enter through the same neighbour offsets as in
+// NbLoad.  Called with every lane of the wave active.
+struct NbWave {
+    static constexpr bool wave = true;
+    unsigned hx;   // per lane: bxm on lane 0, bxp on lane 63, 0 elsewhere
+    __device__ __forceinline__ void trip(const Buf& b, int p, unsigned row, const Col&,
+                                         float& m, float& z, float& q) const {
+        z = ldb(b, p, row);
+        const float h = ldb(b, p, row + hx);
+        m = from_left(h, z);
+        q = from_right(h, z);
+    }
+};
+
 // x-pass of plane p around byte offset `row`.
-template <int P0>
-__device__ __forceinline__ float xpass(const Buf& b, int p, unsigned row, const Col& c, W3 w) {
+template <int P0, class NB>
+__device__ __forceinline__ float xpass(const Buf& b, int p, unsigned row, const Col& c, W3 w,
+                                       const NB& nb) {
     if constexpr (P0 == 0) {
         return ldb(b, p, row);
     } else {
-        float v = w.z * ldb(b, p, row);
-        v = fmaf(w.m, ldb(b, p, row + c.bxm), v);
-        v = fmaf(w.p, ldb(b, p, row + c.bxp), v);
+        float m, z, q;
+        nb.trip(b, p, row, c, m, z, q);
+        float v = w.z * z;
+        v = fmaf(w.m, m, v);
+        v = fmaf(w.p, q, v);
         return v;
     }
 }
 
 // Cross-section pass of one deviation plane around byte offset `cen`.
-template <int LAT, int Q0, int Q1>
+template <int LAT, int Q0, int Q1, class NB>
 __device__ __forceinline__ float hpass(const Buf& b, int p, unsigned cen, const Col& c,
-                                       const float* L) {
+                                       const float* L, const NB& nb) {
     const W3 wx = wsel(Q0, L);
     if constexpr (Lat<LAT>::DIM == 2 || Q1 == 0) {
-        return xpass<Q0>(b, p, cen, c, wx);
+        return xpass<Q0>(b, p, cen, c, wx, nb);
     } else {
         const W3 wy = wsel(Q1, L);
-        float v = wy.z * xpass<Q0>(b, p, cen, c, wx);
-        v = fmaf(wy.m, xpass<Q0>(b, p, cen + c.bym, c, wx), v);
-        v = fmaf(wy.p, xpass<Q0>(b, p, cen + c.byp, c, wx), v);
+        float v = wy.z * xpass<Q0>(b, p, cen, c, wx, nb);
+        v = fmaf(wy.m, xpass<Q0>(b, p, cen + c.bym, c, wx, nb), v);
+        v = fmaf(wy.p, xpass<Q0>(b, p, cen + c.byp, c, wx, nb), v);
         return v;
     }
 }
@@ -138,12 +183,14 @@ struct RhoLayer {
     float c, dxm, dxp, dym, dyp;
 };
 
-template <int LAT>
-__device__ __forceinline__ RhoLayer rho_layer(const Buf& b, int p, unsigned cen, const Col& c) {
+template <int LAT, class NB>
+__device__ __forceinline__ RhoLayer rho_layer(const Buf& b, int p, unsigned cen, const Col& c,
+                                              const NB& nb) {
     RhoLayer r;
-    r.c = ldb(b, p, cen);
-    r.dxm = ldb(b, p, cen + c.bxm) - r.c;
-    r.dxp = ldb(b, p, cen + c.bxp) - r.c;
+    float m, q;
+    nb.trip(b, p, cen, c, m, r.c, q);
+    r.dxm = m - r.c;
+    r.dxp = q - r.c;
     if constexpr (Lat<LAT>::DIM == 3) {
         r.dym = ldb(b, p, cen + c.bym) - r.c;
         r.dyp = ldb(b, p, cen + c.byp) - r.c;
@@ -174,16 +221,16 @@ __device__ __forceinline__ GatherConst gather_const(const LatParams& P, int dim)
 
 #define LBM_HP(CEN)                                                                      \
     ((Fr::p0(a) > 0)                                                                     \
-         ? ((Fr::p1(a) > 0)   ? hpass<LAT, 1, 1>(B, pidx, CEN, col, L)                    \
-            : (Fr::p1(a) < 0) ? hpass<LAT, 1, -1>(B, pidx, CEN, col, L)                   \
-                              : hpass<LAT, 1, 0>(B, pidx, CEN, col, L))                   \
+         ? ((Fr::p1(a) > 0)   ? hpass<LAT, 1, 1>(B, pidx, CEN, col, L, nb)                    \
+            : (Fr::p1(a) < 0) ? hpass<LAT, 1, -1>(B, pidx, CEN, col, L, nb)                   \
+                              : hpass<LAT, 1, 0>(B, pidx, CEN, col, L, nb))                   \
      : (Fr::p0(a) < 0)                                                                   \
-         ? ((Fr::p1(a) > 0)   ? hpass<LAT, -1, 1>(B, pidx, CEN, col, L)                   \
-            : (Fr::p1(a) < 0) ? hpass<LAT, -1, -1>(B, pidx, CEN, col, L)                  \
-                              : hpass<LAT, -1, 0>(B, pidx, CEN, col, L))                  \
-         : ((Fr::p1(a) > 0)   ? hpass<LAT, 0, 1>(B, pidx, CEN, col, L)                    \
-            : (Fr::p1(a) < 0) ? hpass<LAT, 0, -1>(B, pidx, CEN, col, L)                   \
-                              : hpass<LAT, 0, 0>(B, pidx, CEN, col, L)))
+         ? ((Fr::p1(a) > 0)   ? hpass<LAT, -1, 1>(B, pidx, CEN, col, L, nb)                   \
+            : (Fr::p1(a) < 0) ? hpass<LAT, -1, -1>(B, pidx, CEN, col, L, nb)                  \
+                              : hpass<LAT, -1, 0>(B, pidx, CEN, col, L, nb))                  \
+         : ((Fr::p1(a) > 0)   ? hpass<LAT, 0, 1>(B, pidx, CEN, col, L, nb)                    \
+            : (Fr::p1(a) < 0) ? hpass<LAT, 0, -1>(B, pidx, CEN, col, L, nb)                   \
+                              : hpass<LAT, 0, 0>(B, pidx, CEN, col, L, nb)))
 
 // Per-column geometry of a gather (shared by the joint and per-species forms).
 struct ColGeom {
@@ -229,8 +276,9 @@ __device__ __forceinline__ unsigned layer_off(const ColGeom& g, int ml) {
 
 // Species 1 (c = 1) at layer m: exact shift.  f_a(O) = f~_a(O - c_a), or
 // f~_abar(O) when O - c_a is solid (halfway bounce-back); written without
-// branches: a solid source reads the rest population at O itself
-// (difference 0) and the plane of the opposite direction.
+// branches: a solid source reads the rest population at O itself (difference
+// 0) and the plane of the opposite direction.  (Each shifted value is a single
+// read here, so the cross-lane form would not save loads.)
 template <int LAT>
 __device__ __forceinline__ void shift_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int m, unsigned own, float& P0,
@@ -278,16 +326,17 @@ struct Heavy {
 };
 
 // Start the march of a heavier species (planes pb0 .. pb0+Q-1) at layer m0.
-template <int LAT>
+template <int LAT, class NB>
 __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, const ColGeom& g,
-                                            int pb0, const float* L, int m0, Heavy<LAT>& h) {
+                                            int pb0, const float* L, int m0, Heavy<LAT>& h,
+                                            const NB& nb) {
     using Fr = Frame<LAT>;
     constexpr int Q = Lat<LAT>::Q;
     const Col& col = g.col;
     const int lm = nbr(m0, -1, G.nm, g.wm);
     const unsigned cm_ = layer_off(g, lm), c0_ = layer_off(g, m0);
-    h.rl[0] = rho_layer<LAT>(B, pb0, cm_, col);
-    h.rl[1] = rho_layer<LAT>(B, pb0, c0_, col);
+    h.rl[0] = rho_layer<LAT>(B, pb0, cm_, col, nb);
+    h.rl[1] = rho_layer<LAT>(B, pb0, c0_, col, nb);
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
         if (Fr::pm(a) != 0) {
@@ -306,17 +355,17 @@ __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, 
 
 // One layer of a heavier species: second-order interpolation plus the
 // impermeable-wall terms; side is the column's wall side on the wall axis.
-template <int LAT>
+template <int LAT, class NB>
 __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int pb0, const float* L, unsigned own, unsigned nxt,
                                             int side, Heavy<LAT>& h, float& P0,
-                                            float (&F)[Lat<LAT>::Q]) {
+                                            float (&F)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
     constexpr int Q = La::Q;
     constexpr int DIM = La::DIM;
     const Col& col = g.col;
-    h.rl[2] = rho_layer<LAT>(B, pb0, nxt, col);
+    h.rl[2] = rho_layer<LAT>(B, pb0, nxt, col, nb);
     const float rc = h.rl[1].c;
     P0 = rc;
     F[0] = 0.0f;
@@ -327,9 +376,10 @@ __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, 
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const unsigned rr = own + (j == 0 ? col.bym : col.byp);
-            const float cc = ldb(B, pb0, rr);
-            cxm[j] = ldb(B, pb0, rr + col.bxm) - cc;
-            cxp[j] = ldb(B, pb0, rr + col.bxp) - cc;
+            float cm, cc, cp;
+            nb.trip(B, pb0, rr, col, cm, cc, cp);
+            cxm[j] = cm - cc;
+            cxp[j] = cp - cc;
         }
     }
 #pragma unroll
@@ -412,9 +462,10 @@ __device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x,
                                       int m1, Op& op) {
     constexpr int Q = Lat<LAT>::Q;
     const ColGeom g = col_geom<LAT>(G, x, y);
+    const NbLoad nb{};
     Heavy<LAT> h[NS > 1 ? NS - 1 : 1];
 #pragma unroll
-    for (int s = 1; s < NS; ++s) heavy_begin<LAT>(B, G, g, s * Q, G.lam[s], m0, h[s - 1]);
+    for (int s = 1; s < NS; ++s) heavy_begin<LAT>(B, G, g, s * Q, G.lam[s], m0, h[s - 1], nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
@@ -424,21 +475,18 @@ __device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x,
         shift_layer<LAT>(B, G, g, m, own, P0[0], F[0]);
 #pragma unroll
         for (int s = 1; s < NS; ++s)
-            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, side, h[s - 1], P0[s], F[s]);
+            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, side, h[s - 1], P0[s], F[s], nb);
         op(P0, F, m, own);
     }
 }
 
-// The same gather for one species s (uniform over the wave) with weight
-// triple L; calls op(P0, F, m, own) with the species' values.
-template <int LAT, class Op>
-__device__ __forceinline__ void march1(const Buf& B, const GatherConst& G, int s,
-                                       const float (&L)[3], int x, int y, int m0, int m1,
-                                       Op& op) {
+template <int LAT, class NB, class Op>
+__device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, int s,
+                                          const float (&L)[3], const ColGeom& g, int m0, int m1,
+                                          Op& op, const NB& nb) {
     constexpr int Q = Lat<LAT>::Q;
-    const ColGeom g = col_geom<LAT>(G, x, y);
     Heavy<LAT> h;
-    if (s > 0) heavy_begin<LAT>(B, G, g, s * Q, L, m0, h);
+    if (s > 0) heavy_begin<LAT>(B, G, g, s * Q, L, m0, h, nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
@@ -447,9 +495,55 @@ __device__ __forceinline__ void march1(const Buf& B, const GatherConst& G, int s
         if (s == 0)
             shift_layer<LAT>(B, G, g, m, own, P0, F);
         else
-            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_side<LAT>(G, g, m), h, P0, F);
+            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_side<LAT>(G, g, m), h, P0, F, nb);
         op(P0, F, m, own);
     }
+}
+
+// The same gather for one species s (uniform over the wave) with weight
+// triple L; calls op(P0, F, m, own) with the species' values.  With wave_row
+// the wave's 64 lanes are 64 consecutive columns of one row (in order) and the
+// x neighbours are taken across lanes.  lane_zero marks a lane whose reads
+// all return 0.
+template <int LAT, class Op>
+__device__ __forceinline__ void march1(const Buf& B, const GatherConst& G, int s,
+                                       const float (&L)[3], int x, int y, bool lane_zero,
+                                       bool wave_row, int m0, int m1, Op& op) {
+    ColGeom g = col_geom<LAT>(G, x, y);
+    if (lane_zero) g.colbase += kSolid;
+    if (wave_row) {
+        const unsigned lane = __lane_id();
+        NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
+        march1_nb<LAT>(B, G, s, L, g, m0, m1, op, nb);
+    } else {
+        march1_nb<LAT>(B, G, s, L, g, m0, m1, op, NbLoad{});
+    }
+}
+
+// Column of lane `lane` of a tile of 64 columns: x fastest over bx columns,
+// then y (3-D).  Returns whether the lane lies in the lattice; a lane beyond
+// it stores nothing and follows the column after the row's last one (the
+// wrapped column when x is periodic, a lane whose reads return 0 at an x
+// wall: `zero`), and in y the last row.  The last column's right neighbour in
+// the cross-lane gather is then the right value.
+template <int LAT>
+__device__ __forceinline__ bool tile_column(const Tile& T, const LatParams& P, int lane, int bx,
+                                            int& x, int& y, bool& zero) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    x = T.x0 + (DIM == 3 ? lane % bx : lane);
+    y = DIM == 3 ? T.y0 + lane / bx : 0;
+    const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
+    zero = false;
+    if (x >= P.nx) {
+        if (P.wall_axis == 0) {
+            x = P.nx - 1;
+            zero = true;
+        } else {
+            x %= P.nx;
+        }
+    }
+    if (DIM == 3 && y >= P.ny) y = P.ny - 1;
+    return inside;
 }
 
 #undef LBM_HP

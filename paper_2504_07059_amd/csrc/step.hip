@@ -132,14 +132,11 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
     for (int t = t0; t < t1; ++t) {
         const Tile T = tiles[t];
         const LatParams& P = lps[T.lat];
-        const int cx = DIM == 3 ? lane % bx : lane;
-        const int cy = DIM == 3 ? lane / bx : 0;
-        int x = T.x0 + cx, y = DIM == 3 ? T.y0 + cy : 0;
-        // lanes beyond the lattice follow a valid column (every wave must
-        // reach the barriers) and store nothing
-        const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
-        x = x < P.nx ? x : P.nx - 1;
-        if (DIM == 3) y = y < P.ny ? y : P.ny - 1;
+        // lanes beyond the lattice still run (every wave must reach the
+        // barriers) and store nothing
+        int x, y;
+        bool zero;
+        const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Q;
         // the species' own constants, read with the uniform species index
@@ -148,7 +145,8 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         SplitOp<LAT, NS> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                             SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s]},
                             xch, s, lane, inside, false};
-        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, T.m0, T.m1, op);
+        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
+                    T.m1, op);
         bad = bad || op.bad;
         __syncthreads();   // the next tile reuses the exchange buffers
     }
