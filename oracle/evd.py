@@ -71,6 +71,8 @@ class Model:
     walls: Sequence[bool] = (False, False, False)
     n0: Optional[float] = None
     force_field: Optional[torch.Tensor] = None   # [3, nz, ny, nx] overrides g
+    forcing: str = "standard"   # "standard": eq. (CE_forcing_term_discretized);
+                                # "diff": plus S_diff of eq. (improved_forcing_scheme)
 
     def __post_init__(self):
         self.lat = Lattice(self.lattice)
@@ -93,6 +95,8 @@ class Model:
                 raise ValueError("a wall axis needs at least 2 nodes")
         if self.lat.dim == 2 and self.walls[2]:
             raise ValueError("no z walls in 2-D")
+        if self.forcing not in ("standard", "diff"):
+            raise ValueError("forcing must be 'standard' or 'diff'")
 
     def shape_axis(self, a):
         return (self.nx, self.ny, self.nz)[a]
@@ -252,18 +256,50 @@ def forcing_term(model, rho_i, u):
     return w[None, :, None, None, None] * S
 
 
+def theta(model, rho_i, rho, ueq, Y):
+    """Theta_i = sum_j (rho_i rho_j / (rho tau_ij)) (u_i^eq - u_j^eq), the
+    momentum the velocity-difference relaxation removes from species i
+    (eq. CE_theta_definition).  [N, nz, ny, nx, 3]."""
+    N = model.N
+    out = torch.zeros_like(ueq)
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                out[i] = out[i] + (rho_i[i] * rho_i[j] / rho * Y[i, j])[..., None] \
+                    * (ueq[i] - ueq[j])
+    return out
+
+
+def diffusion_forcing(model, th, u):
+    """Diffusion-driven forcing contribution of eq. (improved_forcing_scheme):
+    S_diff = omega (dt/(2 tau_i - dt)) [(e e - c_s^2 I)/c_s^4 . u] . Theta_i,
+    i.e. omega/(2 tau_i - 1) [(e.u)(e.Theta_i) - c_s^2 u.Theta_i]/c_s^4 (dt = 1)."""
+    e = model.velocities()
+    w = model.lat.w
+    cs2 = torch.tensor(model.sound2(), dtype=DTYPE)[:, None, None, None, None]
+    tau = torch.tensor(model.taus(), dtype=DTYPE)[:, None, None, None, None]
+    eu = torch.einsum("nqc,zyxc->nqzyx", e, u)
+    eth = torch.einsum("nqc,nzyxc->nqzyx", e, th)
+    uth = _dot(u[None], th)[:, None]
+    return w[None, :, None, None, None] / (2.0 * tau - 1.0) * (eu * eth - cs2 * uth) / (cs2 * cs2)
+
+
 def collide(model, f):
     """f~ = f + Omega^ii + sum_{j!=i} Omega^ij + (1 - dt/(2 tau_i)) S, with
     Omega^ii = -(f - f^(0))/tau_i                        (eq. BGK_self_collision)
     Omega^ij = -(1/tau_ij)(rho_j/rho) f^(eq)/c_s^2 (e-u).(u_i^eq - u_j^eq)
                                                    (eq. Cross_collision_Sirovich)
-    inside eq. (LBE_forcing)."""
+    inside eq. (LBE_forcing).  With model.forcing == "diff" the forcing term
+    S includes the diffusion-driven contribution S_diff of eq.
+    (improved_forcing_scheme)."""
     N = model.N
     rho_i, ueq = species_moments(model, f)
     rho, u, n, p = mixture(model, rho_i, ueq)
     Y = cross_relaxation(model, rho_i, rho, n, p)
     feq, f0 = equilibria(model, rho_i, ueq, u)
     S = forcing_term(model, rho_i, u)
+    if model.forcing == "diff":
+        S = S + diffusion_forcing(model, theta(model, rho_i, rho, ueq, Y), u)
     e = model.velocities()
     cs2 = model.sound2()
     tau = model.taus()
@@ -409,17 +445,11 @@ def observables(model, f):
     Y = cross_relaxation(model, rho_i, rho, n, p)
     M = torch.tensor(model.M, dtype=DTYPE)
     x = rho_i / (M[:, None, None, None] * n)
-    N = model.N
-    theta = torch.zeros_like(ueq)
-    for i in range(N):
-        for j in range(N):
-            if i != j:
-                theta[i] = theta[i] + (rho_i[i] * rho_i[j] / rho * Y[i, j])[..., None] \
-                    * (ueq[i] - ueq[j])
+    th = theta(model, rho_i, rho, ueq, Y)
     safe = torch.where(rho_i == 0, torch.ones_like(rho_i), rho_i)
-    u_real = ueq - 0.5 * theta / safe[..., None]
+    u_real = ueq - 0.5 * th / safe[..., None]
     return {
         "rho_i": rho_i, "ueq": ueq, "rho": rho, "u": u, "n": n, "p": p,
-        "x": x, "tau_inv": Y, "theta": theta, "u_i": u_real,
+        "x": x, "tau_inv": Y, "theta": th, "u_i": u_real,
         "mass": rho_i.sum(dim=(1, 2, 3)),
     }
