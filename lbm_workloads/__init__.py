@@ -53,6 +53,7 @@ class Workload:
     seed: int = 0
     x0_args: dict = field(default_factory=dict)
     n0: Optional[float] = None
+    forcing: str = "standard"    # "standard", or "diff": plus the diffusion-driven term
 
     @property
     def n_species(self):

@@ -11,7 +11,9 @@
 //   1/tau_ij from eq. (relation_tauij_diff_coeff)         (tau_solve)
 //   f~ = f - (f - f^(0))/tau_i + sum_j Omega^ij + (1 - 1/(2 tau_i)) S
 //        with f^(eq), f^(0) of eq. (feqi0), Omega^ij of eq.
-//        (Cross_collision_Sirovich), S of eq. (CE_forcing_term_discretized);
+//        (Cross_collision_Sirovich), S of eq. (CE_forcing_term_discretized),
+//        plus (forcing 1) the diffusion-driven contribution S_diff of eq.
+//        (improved_forcing_scheme) with Theta_i of eq. (CE_theta_definition);
 // everything is evaluated as a deviation from w_a rho_i (collision conserves
 // rho_i).  The result is stored as P0' = f~_0 and g_a = f~_a - (w_a/w_0) P0'
 // (a >= 1); the rounding error of P0' is handed to the g_a in proportion to
@@ -24,7 +26,7 @@
 namespace lbmmc {
 
 struct CollConst {
-    float c[MAXS], inv_cs2[MAXS], inv_tau[MAXS], fpref[MAXS], invM[MAXS];
+    float c[MAXS], inv_cs2[MAXS], inv_tau[MAXS], fpref[MAXS], invM[MAXS], kdiff[MAXS];
     float K[MAXS][MAXS];
     float g[3];
 };
@@ -34,7 +36,7 @@ __device__ __forceinline__ CollConst coll_const(const LatParams& P) {
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
         C.c[s] = P.c[s]; C.inv_cs2[s] = P.inv_cs2[s]; C.inv_tau[s] = P.inv_tau[s];
-        C.fpref[s] = P.fpref[s]; C.invM[s] = P.invM[s];
+        C.fpref[s] = P.fpref[s]; C.invM[s] = P.invM[s]; C.kdiff[s] = P.kdiff[s];
 #pragma unroll
         for (int t = 0; t < MAXS; ++t) C.K[s][t] = P.K[s][t];
     }
@@ -190,16 +192,20 @@ __device__ __forceinline__ void friction(int i, const float (&rho)[NS], const fl
     }
 }
 
-// Per-species constants of one species.
+// Per-species constants of one species (kd = 1/(2 tau - 1), used with FRC 1).
 struct SpeciesConst {
-    float c, ics, itau, fp;
+    float c, ics, itau, fp, kd;
 };
 
 // Collision of one species at one node, given the mixture, its friction
 // vector V and its own moments.  On return P0 holds the new stored rest
 // population and F[a] (a >= 1) the stored deviations g_a.  Returns false if a
-// result is not finite.
-template <int LAT>
+// result is not finite.  FRC 1 adds S_diff: with Theta_i = rho_i V_i,
+//   S_diff = w/(2 tau - 1) [(e.u)(e.Theta) - c_s^2 u.Theta]/c_s^4,
+// which enters the collision with the same factor (1 - 1/(2 tau)) as S, so
+// the forcing bracket becomes e.F - u.F + t e.F + kd (t e.Theta - u.Theta)
+//   = (e.F - u.G) + t e.G,   G = F + kd Theta.
+template <int LAT, int FRC>
 __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const float (&g)[3],
                                                 float rho_i, float dlt_i, const float (&ue_i)[3],
                                                 const Mix& M, const float (&V)[3], float& P0,
@@ -207,8 +213,9 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
     constexpr int Q = Lat<LAT>::Q;
     using L = Lat<LAT>;
     const float c = K.c, ics = K.ics, itau = K.itau, fp = K.fp;
-    float du[3], T[3], Z[3], Fc[3];
-    float udu = 0.0f, uV = 0.0f, uF = 0.0f;
+    float du[3], T[3], Z[3], Fc[3], Gc[3];
+    float udu = 0.0f, uV = 0.0f, uF = 0.0f, uG = 0.0f;
+    const float kr = FRC ? K.kd * rho_i : 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         du[d] = ue_i[d] - M.U[d];
@@ -219,7 +226,13 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
         T[d] = ics * c * M.U[d];               // t_a = c_a . T = e.u / c_s^2
         Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
         Fc[d] = c * Fd;                         // c_a . Fc = e.F
+        if (FRC) {
+            const float Gd = fmaf(kr, V[d], Fd);
+            uG = fmaf(M.U[d], Gd, uG);
+            Gc[d] = c * Gd;                     // c_a . Gc = e.G
+        }
     }
+    if (!FRC) uG = uF;
     const float b0 = -0.5f * M.uu * ics;
     const float z0 = fmaf(itau, udu, -uV);
     float sgt = 0.0f;
@@ -228,14 +241,15 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
         // f^(eq) - w rho = w rho [t (1 + t/2) + b0],  t = e.u/c_s^2
         // f~ - w rho = h + (feqd - h)/tau
         //            + feq/c_s^2 [ (e.du - u.du)/tau - (e.V - u.V) ]     (f^(0), Omega^ij)
-        //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.F + t e.F ]      (S)
+        //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.G + t e.G ]      (S, S_diff)
         const float wr = L::w(a) * rho_i;
         const float t = cdot<LAT>(a, T[0], T[1], T[2]);
         const float feqd = wr * fmaf(t, fmaf(0.5f, t, 1.0f), b0);
         const float A = (wr + feqd) * ics;
         const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
         const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
-        const float Sp = fmaf(t, eF, eF - uF);
+        const float eG = FRC ? cdot<LAT>(a, Gc[0], Gc[1], Gc[2]) : eF;
+        const float Sp = fmaf(t, eG, eF - uG);
         const float h = fmaf(-L::w(a), dlt_i, F[a]);   // f_a - w_a rho
         // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
         // rounded coefficients of the latter do not sum to exactly 1, which
@@ -255,7 +269,7 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
 // Collision of one node, all species.  On return P0[s] holds the new stored
 // rest population and F[s][a] (a >= 1) the stored deviations g_a.  Returns
 // false if a result is not finite.
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
                                         const CollConst& C) {
     float rho[NS], dlt[NS], ue[NS][3];
@@ -269,8 +283,8 @@ __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>
     for (int i = 0; i < NS; ++i) {
         float V[3];
         friction<NS>(i, rho, ue, y, M.iR, V);
-        const SpeciesConst K{C.c[i], C.inv_cs2[i], C.inv_tau[i], C.fpref[i]};
-        ok = collide_species<LAT>(K, C.g, rho[i], dlt[i], ue[i], M, V, P0[i], F[i]) && ok;
+        const SpeciesConst K{C.c[i], C.inv_cs2[i], C.inv_tau[i], C.fpref[i], C.kdiff[i]};
+        ok = collide_species<LAT, FRC>(K, C.g, rho[i], dlt[i], ue[i], M, V, P0[i], F[i]) && ok;
     }
     return ok;
 }

@@ -112,8 +112,10 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         if (q.lattice == LBM_MC_D2Q9 && q.g[2] != 0.0)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: g[2] must be 0 in 2-D", l);
         if (!std::isfinite(q.n0)) return fail(LBM_MC_ERR_INVALID, "lattice %d: n0 not finite", l);
-        if (q.forcing != 0)
-            return fail(LBM_MC_ERR_UNSUPPORTED, "lattice %d: only forcing = 0 is provided", l);
+        if (q.forcing != 0 && q.forcing != 1)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: forcing must be 0 or 1", l);
+        if (q.forcing != p[0].forcing)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: every lattice needs the same forcing", l);
         if (q.reserved != 0) return fail(LBM_MC_ERR_INVALID, "lattice %d: reserved must be 0", l);
     }
     return LBM_MC_OK;
@@ -518,6 +520,7 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.bx = c->tune.bx;
     L.by = c->tune.by;
     L.split = c->tune.split;
+    L.forcing = c->params[0].forcing;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -611,6 +614,8 @@ lbm_mc_status build_adj_tiles(lbm_mc_ctx* c) {
 lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (c->L != 1) return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: batched contexts are not supported");
+    if (c->params[0].forcing != 0)
+        return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: only forcing = 0 is differentiated");
     const size_t bytes = (size_t)c->layout.total * sizeof(float);
     if (!c->dmu) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
@@ -759,6 +764,7 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
         for (int a = 0; a < 3; ++a)
             if (q.bc[a] == LBM_MC_WALL) P.wall_axis = a;
         P.n_species = q.n_species;
+        P.forcing = q.forcing;
         for (int i = 0; i < MAXS; ++i) {
             if (i < nm.N) {
                 exact_triple(nm.c[i], P.lam[i]);
@@ -766,6 +772,7 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
                 P.inv_cs2[i] = (float)(1.0 / nm.cs2[i]);
                 P.inv_tau[i] = (float)(1.0 / nm.tau[i]);
                 P.fpref[i] = (float)(1.0 - 0.5 / nm.tau[i]);
+                P.kdiff[i] = q.forcing == 1 ? (float)(1.0 / (2.0 * nm.tau[i] - 1.0)) : 0.0f;
                 P.invM[i] = (float)(1.0 / nm.M[i]);
                 P.M[i] = (float)nm.M[i];
                 for (int j = 0; j < nm.N; ++j) {

@@ -2,6 +2,9 @@
 // observables with their FP64 reductions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "collide.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -20,7 +23,7 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
     t1 = (int)((int64_t)(vb + 1) * ntiles / G);
 }
 
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -28,7 +31,7 @@ struct StepOp {
     bool bad;
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int,
                                                unsigned own) {
-        if (!collide<LAT, NS>(P0, F, C)) bad = true;
+        if (!collide<LAT, NS, FRC>(P0, F, C)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             stb(D, s * Q, own, P0[s]);
@@ -38,7 +41,7 @@ struct StepOp {
     }
 };
 
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
                                               const LatParams* __restrict__ lps,
                                               const Tile* __restrict__ tiles, int ntiles,
@@ -55,7 +58,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false};
+        StepOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false};
         march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
@@ -70,7 +73,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, so several times more waves fit on a SIMD.
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 struct SplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -104,7 +107,7 @@ struct SplitOp {
             if (i != s) continue;
             friction<NS>(i, rho, ue, y, M.iR, V);
         }
-        const bool ok = collide_species<LAT>(K, C.g, rho_s, dlt_s, ue_s, M, V, P0, F) &&
+        const bool ok = collide_species<LAT, FRC>(K, C.g, rho_s, dlt_s, ue_s, M, V, P0, F) &&
                         isfinite(M.R);
         if (inside) {
             stb(D, s * Q, own, P0);
@@ -115,7 +118,7 @@ struct SplitOp {
     }
 };
 
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
                                                     float* __restrict__ dst,
                                                     const LatParams* __restrict__ lps,
@@ -142,8 +145,9 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         // the species' own constants, read with the uniform species index
         // (scalar loads; no run-time indexing of register arrays)
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-        SplitOp<LAT, NS> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
-                            SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s]},
+        SplitOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+                                 SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
+                                              P.kdiff[s]},
                             xch, s, lane, inside, false};
         march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
                     T.m1, op);
@@ -158,7 +162,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
 // velocity), rho_i = x_i M_i n0, evaluated in double and stored as
 // P0 = f_0 and g_a = f_a - (w_a/w_0) P0 + w_a (f_0 - P0)/(1 - w_0) in f0_out;
 // then one collision, stored in ft_out.
-template <int LAT, int NS>
+template <int LAT, int NS, int FRC>
 __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps, int lat,
                                               const double* __restrict__ x0,
                                               float* __restrict__ f0_out,
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
             for (int a = 1; a < Q; ++a) f0_out[(int64_t)(s * Q + a) * P.plane + own] = F[s][a];
         }
         // f(0) as gather output: P0 and F_a = f_a - w_a r* = g_a
-        if (!collide<LAT, NS>(P0, F, C)) bad = true;
+        if (!collide<LAT, NS, FRC>(P0, F, C)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             ft_out[(int64_t)(s * Q) * P.plane + own] = P0[s];
@@ -341,70 +345,53 @@ __global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lp
 }
 
 // ---------------------------------------------------------------- launchers
-template <int LAT, int NS>
-static hipError_t launch_step_t(const Launch& L) {
-    dim3 block(L.bx, L.by);
-    hipLaunchKernelGGL((k_step<LAT, NS>), dim3(L.grid), block, 0, L.stream, L.src, L.dst, L.lp,
-                       L.tiles, L.ntiles, L.flag);
-    return hipGetLastError();
-}
-
-template <int LAT, int NS>
-static hipError_t launch_split_t(const Launch& L) {
-    hipLaunchKernelGGL((k_step_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0, L.stream, L.src,
-                       L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_step(int lattice, int ns, const Launch& L) {
-    if (L.split) {
-        if (L.bx * L.by != 64) return hipErrorInvalidValue;
-        if (lattice == 0) {
-            if (ns == 2) return launch_split_t<0, 2>(L);
-            if (ns == 3) return launch_split_t<0, 3>(L);
-            if (ns == 4) return launch_split_t<0, 4>(L);
-        } else {
-            if (ns == 2) return launch_split_t<1, 2>(L);
-            if (ns == 3) return launch_split_t<1, 3>(L);
-            if (ns == 4) return launch_split_t<1, 4>(L);
-        }
+// Calls fn(lattice, species count, forcing) with the three as compile-time
+// constants.
+template <typename Fn>
+static hipError_t by_shape(int lattice, int ns, int frc, Fn&& fn) {
+    using std::integral_constant;
+    auto with_frc = [&](auto lat, auto n) -> hipError_t {
+        if (frc == 0) return fn(lat, n, integral_constant<int, 0>{});
+        if (frc == 1) return fn(lat, n, integral_constant<int, 1>{});
         return hipErrorInvalidValue;
-    }
-    if (lattice == 0) {
-        if (ns == 2) return launch_step_t<0, 2>(L);
-        if (ns == 3) return launch_step_t<0, 3>(L);
-        if (ns == 4) return launch_step_t<0, 4>(L);
-    } else {
-        if (ns == 2) return launch_step_t<1, 2>(L);
-        if (ns == 3) return launch_step_t<1, 3>(L);
-        if (ns == 4) return launch_step_t<1, 4>(L);
-    }
+    };
+    auto with_ns = [&](auto lat) -> hipError_t {
+        if (ns == 2) return with_frc(lat, integral_constant<int, 2>{});
+        if (ns == 3) return with_frc(lat, integral_constant<int, 3>{});
+        if (ns == 4) return with_frc(lat, integral_constant<int, 4>{});
+        return hipErrorInvalidValue;
+    };
+    if (lattice == 0) return with_ns(integral_constant<int, 0>{});
+    if (lattice == 1) return with_ns(integral_constant<int, 1>{});
     return hipErrorInvalidValue;
 }
 
-template <int LAT, int NS>
-static hipError_t launch_init_t(const LatParams* lp, int lat, const LatParams& h, const double* x0,
-                                float* f0, float* ft, unsigned* flag, hipStream_t s) {
-    const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
-    int64_t blocks = (nodes + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((k_init<LAT, NS>), dim3((unsigned)blocks), dim3(256), 0, s, lp, lat, x0, f0,
-                       ft, flag);
-    return hipGetLastError();
+hipError_t launch_step(int lattice, int ns, const Launch& L) {
+    if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
+    return by_shape(lattice, ns, L.forcing, [&](auto lat, auto n, auto frc) {
+        constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
+                      FRC = decltype(frc)::value;
+        if (L.split)
+            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC>), dim3(L.grid), dim3(64, NS), 0,
+                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.flag);
+        else
+            hipLaunchKernelGGL((k_step<LAT, NS, FRC>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.flag);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const LatParams& h,
                        const double* x0, float* f0, float* ft, unsigned* flag, hipStream_t s) {
-    if (lattice == 0) {
-        if (ns == 2) return launch_init_t<0, 2>(lp, lat, h, x0, f0, ft, flag, s);
-        if (ns == 3) return launch_init_t<0, 3>(lp, lat, h, x0, f0, ft, flag, s);
-        if (ns == 4) return launch_init_t<0, 4>(lp, lat, h, x0, f0, ft, flag, s);
-    } else {
-        if (ns == 2) return launch_init_t<1, 2>(lp, lat, h, x0, f0, ft, flag, s);
-        if (ns == 3) return launch_init_t<1, 3>(lp, lat, h, x0, f0, ft, flag, s);
-        if (ns == 4) return launch_init_t<1, 4>(lp, lat, h, x0, f0, ft, flag, s);
-    }
-    return hipErrorInvalidValue;
+    const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
+    const int64_t blocks = std::min<int64_t>((nodes + 255) / 256, 65536);
+    return by_shape(lattice, ns, h.forcing, [&](auto la, auto n, auto frc) {
+        constexpr int LAT = decltype(la)::value, NS = decltype(n)::value,
+                      FRC = decltype(frc)::value;
+        hipLaunchKernelGGL((k_init<LAT, NS, FRC>), dim3((unsigned)blocks), dim3(256), 0, s, lp,
+                           lat, x0, f0, ft, flag);
+        return hipGetLastError();
+    });
 }
 
 template <int LAT, int NS>

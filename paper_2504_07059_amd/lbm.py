@@ -15,8 +15,9 @@ LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
 
 
 def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
-                walls=(False, False, False), n0=0.0):
-    """Fill one lbm_mc_params struct."""
+                walls=(False, False, False), n0=0.0, forcing=0):
+    """Fill one lbm_mc_params struct (forcing: 0 or "standard" for the
+    standard forcing term, 1 or "diff" to add the diffusion-driven term)."""
     p = Params()
     p.lattice = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}[lattice] if isinstance(lattice, str) \
         else int(lattice)
@@ -33,14 +34,14 @@ def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
     for a in range(3):
         p.g[a] = float(g[a])
     p.n0 = float(n0 or 0.0)
-    p.forcing = 0
+    p.forcing = {"standard": 0, "diff": 1}[forcing] if isinstance(forcing, str) else int(forcing)
     p.reserved = 0
     return p
 
 
 def params_from_workload(w):
     return make_params(w.lattice, w.nx, w.ny, w.nz, w.masses, w.diff, w.tau1, w.g,
-                       w.walls, w.n0 or 0.0)
+                       w.walls, w.n0 or 0.0, w.forcing)
 
 
 def _arr(params):

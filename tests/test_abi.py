@@ -108,6 +108,19 @@ def test_check_rejects_invalid_problems(mutate, status):
     assert msg
 
 
+def test_check_forcing_values():
+    """forcing 0 (standard) and 1 (plus S_diff) are accepted, other values
+    rejected; a batch must share one forcing."""
+    from paper_2504_07059_amd.lbm import check_problem
+    for forcing, status in ((0, 0), (1, 0), ("diff", 0), (2, 1), (-1, 1)):
+        p = _tube(forcing=forcing)
+        st, _, msg = check_problem(p, _x0(p))
+        assert st == status, (forcing, msg)
+    a, b = _tube(forcing=0), _tube(forcing=1)
+    st, _, msg = check_problem([a, b], np.concatenate([_x0(a), _x0(b)]))
+    assert st == 1 and "forcing" in msg
+
+
 def test_check_rejects_bad_compositions_and_diffusivities():
     from paper_2504_07059_amd.lbm import check_problem
     p = _tube()

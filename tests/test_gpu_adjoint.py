@@ -298,3 +298,30 @@ def test_misfit_gradient_full_tube_matches_stored_oracle():
     assert _rel(L, G["loss"]) < 1e-3, (L, G["loss"])
     for u, v in zip(dp + dg[:1], G["grad_pairs"] + G["grad_g"][:1]):
         assert _rel(u, v) < GRAD_RTOL, (u, v)
+
+
+def test_adjoint_rejects_the_diffusion_forcing():
+    """The reverse step differentiates the standard forcing only: a context
+    with forcing 1 gets UNSUPPORTED from the adjoint entry points, and its
+    forward stepping is unaffected."""
+    import dataclasses
+    lbm = _lbm()
+    w = dataclasses.replace(CASES[0], forcing="diff")
+    _announce(f"adjoint rejects forcing 1 {w.name}")
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    sim.step(2)
+    s_prev = sim.buffers()[0].clone()
+    lam_in = torch.zeros_like(s_prev)
+    lam_out = torch.zeros_like(s_prev)
+    grad = torch.zeros(w.n_species * (w.n_species - 1) // 2 + 3, dtype=torch.float64,
+                       device=s_prev.device)
+    from paper_2504_07059_amd._lib import LbmError
+    with pytest.raises(LbmError) as e:
+        sim.adjoint_step(s_prev, lam_in, lam_out, grad)
+    assert e.value.status == 2 and "forcing" in str(e.value)
+    with pytest.raises(LbmError) as e:
+        sim.adjoint_init(lam_in, grad)
+    assert e.value.status == 2
+    sim.step(2)
+    sim.sync()
+    sim.close()

@@ -5,6 +5,7 @@ the oracle; per-species mass drift below 1e-6; post-collision populations
 within 2e-6 of the oracle relative to the largest population (FP32 rounding
 of a few dozen steps).  Integer-like properties (determinism, independence of
 the execution shape, resume) are bit-exact."""
+import dataclasses
 import json
 import os
 
@@ -31,7 +32,8 @@ def _lbm():
 
 def _oracle_model(w, ny=None):
     return evd.Model(w.lattice, w.nx, w.ny if ny is None else ny, w.nz, w.masses,
-                     torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+                     torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g, walls=w.walls, n0=w.n0,
+                     forcing=w.forcing)
 
 
 def _announce(msg):
@@ -118,6 +120,28 @@ def test_small_lattices_match_oracle_species_split(w):
     """The species-split variant on the same cases."""
     _announce(f"{w.name} split")
     dx, df, drift, dmass = _compare(w, w.steps, tuning=_split_shape(w))
+    assert dx < X_TOL, dx
+    assert df < F_RTOL, df
+    assert drift < MASS_TOL, drift
+    assert dmass < MASS_TOL, dmass
+
+
+DIFF_CASES = [dataclasses.replace(w, forcing="diff") for w in SMALL
+              if w.name in ("d2q9_n3_xwall", "d2q9_n4_periodic", "d3q19_n4_zwall",
+                            "d3q19_n3_ywall")]
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["joint", "split"])
+@pytest.mark.parametrize("w", DIFF_CASES, ids=[w.name for w in DIFF_CASES])
+def test_diffusion_forcing_matches_oracle(w, variant):
+    """forcing 1: the collision adds the diffusion-driven contribution S_diff
+    of eq. (improved_forcing_scheme); against the oracle's "diff" model, in
+    both execution variants.  On these cases S_diff moves the populations by
+    about 1e-3 of their size after the run, far above the tolerance."""
+    _announce(f"{w.name} S_diff variant {variant}")
+    tuning = _split_shape(w) if variant else ((64, 1, 4, 0, 0) if w.lattice == "D2Q9"
+                                              else (16, 4, 3, 0, 0))
+    dx, df, drift, dmass = _compare(w, w.steps, tuning=tuning)
     assert dx < X_TOL, dx
     assert df < F_RTOL, df
     assert drift < MASS_TOL, drift
