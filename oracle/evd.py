@@ -31,7 +31,13 @@ Readings taken where the paper is silent (each repeated at its function):
   R4 a species with rho_i = 0 at a node takes u_i^eq = F_i/(2 rho_i) -> k_i/2
      (any finite value gives the same populations, as everything it enters is
      multiplied by rho_i);
-  R5 pressure p = n M_1 c_{s,1}^2 with c_{s,1}^2 = 1/3 (standard D2Q9 value).
+  R5 pressure p = n M_1 c_{s,1}^2 with c_{s,1}^2 = 1/3 (standard D2Q9 value);
+  R6 the gradients in the pressure and density forcing contributions of
+     eq. (improved_forcing_scheme) are taken from the densities of the
+     streamed populations at the same time level, by second-order central
+     differences along each lattice axis (periodic axes wrap); at a node next
+     to a wall the second-order one-sided difference into the fluid is used
+     (a wall axis then needs at least 3 nodes).
 """
 import math
 from dataclasses import dataclass, field
@@ -72,7 +78,9 @@ class Model:
     n0: Optional[float] = None
     force_field: Optional[torch.Tensor] = None   # [3, nz, ny, nx] overrides g
     forcing: str = "standard"   # "standard": eq. (CE_forcing_term_discretized);
-                                # "diff": plus S_diff of eq. (improved_forcing_scheme)
+                                # "diff": plus S_diff of eq. (improved_forcing_scheme);
+                                # "full": the whole of eq. (improved_forcing_scheme),
+                                # i.e. - S_p + S_rho + S_diff
 
     def __post_init__(self):
         self.lat = Lattice(self.lattice)
@@ -95,8 +103,12 @@ class Model:
                 raise ValueError("a wall axis needs at least 2 nodes")
         if self.lat.dim == 2 and self.walls[2]:
             raise ValueError("no z walls in 2-D")
-        if self.forcing not in ("standard", "diff"):
-            raise ValueError("forcing must be 'standard' or 'diff'")
+        if self.forcing not in ("standard", "diff", "full"):
+            raise ValueError("forcing must be 'standard', 'diff' or 'full'")
+        if self.forcing == "full":
+            for a in range(3):
+                if self.walls[a] and self.shape_axis(a) < 3:
+                    raise ValueError("the full forcing needs >= 3 nodes on a wall axis")
 
     def shape_axis(self, a):
         return (self.nx, self.ny, self.nz)[a]
@@ -284,6 +296,67 @@ def diffusion_forcing(model, th, u):
     return w[None, :, None, None, None] / (2.0 * tau - 1.0) * (eu * eth - cs2 * uth) / (cs2 * cs2)
 
 
+def gradient(model, phi):
+    """Discrete gradient of a node field phi [nz, ny, nx] (reading R6):
+    (phi(x+1) - phi(x-1))/2 along each lattice axis, wrapped on periodic
+    axes; on a wall axis the first and last nodes take the one-sided
+    differences (-3 phi_0 + 4 phi_1 - phi_2)/2 and
+    (3 phi_{n-1} - 4 phi_{n-2} + phi_{n-3})/2.  Returns [nz, ny, nx, 3]
+    (the z component is 0 in 2-D)."""
+    out = torch.zeros(phi.shape + (3,), dtype=DTYPE)
+    for a in range(model.lat.dim):
+        d = AXIS_DIM[a]
+        n = phi.shape[d]
+        if model.walls[a]:
+            g = torch.zeros_like(phi)
+            idx = lambda i: torch.tensor([i])
+            sel = lambda i: phi.index_select(d, idx(i))
+            for i in range(n):
+                if i == 0:
+                    v = (-3.0 * sel(0) + 4.0 * sel(1) - sel(2)) / 2.0
+                elif i == n - 1:
+                    v = (3.0 * sel(n - 1) - 4.0 * sel(n - 2) + sel(n - 3)) / 2.0
+                else:
+                    v = (sel(i + 1) - sel(i - 1)) / 2.0
+                g.index_copy_(d, idx(i), v)
+        else:
+            g = (torch.roll(phi, -1, dims=d) - torch.roll(phi, 1, dims=d)) / 2.0
+        out[..., a] = g
+    return out
+
+
+def pressure_forcing(model, rho_i, u):
+    """Pressure contribution of eq. (improved_forcing_scheme):
+    S_p = omega [(e e - c_s^2 I)/c_s^4 . u] . grad(rho_i c_s^2)
+        = omega [(e.u)(e.G) - c_s^2 u.G]/c_s^4,  G = c_s^2 grad rho_i
+    (c_s of species i is constant); gradient of reading R6."""
+    e = model.velocities()
+    w = model.lat.w
+    cs2l = model.sound2()
+    G = torch.stack([cs2l[i] * gradient(model, rho_i[i]) for i in range(model.N)])
+    cs2 = torch.tensor(cs2l, dtype=DTYPE)[:, None, None, None, None]
+    eu = torch.einsum("nqc,zyxc->nqzyx", e, u)
+    eG = torch.einsum("nqc,nzyxc->nqzyx", e, G)
+    uG = _dot(u[None], G)[:, None]
+    return w[None, :, None, None, None] * (eu * eG - cs2 * uG) / (cs2 * cs2)
+
+
+def density_forcing(model, rho_i, rho, ueq):
+    """Density contribution of eq. (improved_forcing_scheme):
+    S_rho = omega [(e e - c_s^2 I)/c_s^2 . u_i^eq] . (w_i grad rho)
+          = omega w_i [(e.u_i^eq)(e.grad rho) - c_s^2 u_i^eq.grad rho]/c_s^2,
+    w_i = rho_i/rho the mass fraction; gradient of reading R6."""
+    e = model.velocities()
+    w = model.lat.w
+    cs2 = torch.tensor(model.sound2(), dtype=DTYPE)[:, None, None, None, None]
+    gr = gradient(model, rho)                               # [nz, ny, nx, 3]
+    eu = torch.einsum("nqc,nzyxc->nqzyx", e, ueq)
+    eg = torch.einsum("nqc,zyxc->nqzyx", e, gr)
+    ug = _dot(ueq, gr[None])[:, None]
+    wi = (rho_i / rho)[:, None]
+    return w[None, :, None, None, None] * wi * (eu * eg - cs2 * ug) / cs2
+
+
 def collide(model, f):
     """f~ = f + Omega^ii + sum_{j!=i} Omega^ij + (1 - dt/(2 tau_i)) S, with
     Omega^ii = -(f - f^(0))/tau_i                        (eq. BGK_self_collision)
@@ -291,15 +364,18 @@ def collide(model, f):
                                                    (eq. Cross_collision_Sirovich)
     inside eq. (LBE_forcing).  With model.forcing == "diff" the forcing term
     S includes the diffusion-driven contribution S_diff of eq.
-    (improved_forcing_scheme)."""
+    (improved_forcing_scheme); with "full" it is that whole equation,
+    S - S_p + S_rho + S_diff."""
     N = model.N
     rho_i, ueq = species_moments(model, f)
     rho, u, n, p = mixture(model, rho_i, ueq)
     Y = cross_relaxation(model, rho_i, rho, n, p)
     feq, f0 = equilibria(model, rho_i, ueq, u)
     S = forcing_term(model, rho_i, u)
-    if model.forcing == "diff":
+    if model.forcing in ("diff", "full"):
         S = S + diffusion_forcing(model, theta(model, rho_i, rho, ueq, Y), u)
+    if model.forcing == "full":
+        S = S - pressure_forcing(model, rho_i, u) + density_forcing(model, rho_i, rho, ueq)
     e = model.velocities()
     cs2 = model.sound2()
     tau = model.taus()
