@@ -53,7 +53,8 @@ class Workload:
     seed: int = 0
     x0_args: dict = field(default_factory=dict)
     n0: Optional[float] = None
-    forcing: str = "standard"    # "standard", or "diff": plus the diffusion-driven term
+    forcing: str = "standard"    # "standard"; "diff": plus the diffusion-driven term;
+                                 # "full": the whole corrected forcing
 
     @property
     def n_species(self):

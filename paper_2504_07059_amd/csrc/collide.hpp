@@ -13,7 +13,9 @@
 //        with f^(eq), f^(0) of eq. (feqi0), Omega^ij of eq.
 //        (Cross_collision_Sirovich), S of eq. (CE_forcing_term_discretized),
 //        plus (forcing 1) the diffusion-driven contribution S_diff of eq.
-//        (improved_forcing_scheme) with Theta_i of eq. (CE_theta_definition);
+//        (improved_forcing_scheme) with Theta_i of eq. (CE_theta_definition),
+//        or (forcing 2) that whole equation, - S_p + S_rho + S_diff, with
+//        the density gradients of field_grad;
 // everything is evaluated as a deviation from w_a rho_i (collision conserves
 // rho_i).  The result is stored as P0' = f~_0 and g_a = f~_a - (w_a/w_0) P0'
 // (a >= 1); the rounding error of P0' is handed to the g_a in proportion to
@@ -26,7 +28,7 @@
 namespace lbmmc {
 
 struct CollConst {
-    float c[MAXS], inv_cs2[MAXS], inv_tau[MAXS], fpref[MAXS], invM[MAXS], kdiff[MAXS];
+    float c[MAXS], inv_cs2[MAXS], inv_tau[MAXS], fpref[MAXS], invM[MAXS], kdiff[MAXS], cs2[MAXS];
     float K[MAXS][MAXS];
     float g[3];
 };
@@ -37,6 +39,7 @@ __device__ __forceinline__ CollConst coll_const(const LatParams& P) {
     for (int s = 0; s < MAXS; ++s) {
         C.c[s] = P.c[s]; C.inv_cs2[s] = P.inv_cs2[s]; C.inv_tau[s] = P.inv_tau[s];
         C.fpref[s] = P.fpref[s]; C.invM[s] = P.invM[s]; C.kdiff[s] = P.kdiff[s];
+        C.cs2[s] = P.cs2[s];
 #pragma unroll
         for (int t = 0; t < MAXS; ++t) C.K[s][t] = P.K[s][t];
     }
@@ -192,10 +195,47 @@ __device__ __forceinline__ void friction(int i, const float (&rho)[NS], const fl
     }
 }
 
-// Per-species constants of one species (kd = 1/(2 tau - 1), used with FRC 1).
+// Per-species constants of one species (kd = 1/(2 tau - 1), used with FRC >= 1;
+// cs2 = c_s^2, used with FRC 2).
 struct SpeciesConst {
-    float c, ics, itau, fp, kd;
+    float c, ics, itau, fp, kd, cs2;
 };
+
+// Density gradients at a node (FRC 2): of the species' own density and of
+// the mixture density.
+struct Grads {
+    float gi[3], gm[3];
+};
+
+// Derivative along one axis of a node field, at index i of n nodes (reading
+// of the paper's silent discretisation): (phi(i+1) - phi(i-1))/2, wrapped on
+// a periodic axis; on a wall axis (n >= 3) the first and last nodes take the
+// one-sided second-order differences (-3 phi_0 + 4 phi_1 - phi_2)/2 and
+// (3 phi_{n-1} - 4 phi_{n-2} + phi_{n-3})/2.  at(j) reads the field at index j.
+template <class At>
+__device__ __forceinline__ float axis_diff(At at, int i, int n, bool wall) {
+    if (wall) {
+        if (i == 0) return 0.5f * (fmaf(4.0f, at(1), -3.0f * at(0)) - at(2));
+        if (i == n - 1) return 0.5f * (fmaf(3.0f, at(n - 1), at(n - 3)) - 4.0f * at(n - 2));
+        return 0.5f * (at(i + 1) - at(i - 1));
+    }
+    const int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
+    return 0.5f * (at(ip) - at(im));
+}
+
+// Gradient of a dense node field (node index (z ny + y) nx + x) at (x, y, z)
+// of a lattice with the given shape and wall axis (-1: none).
+template <int DIM, class Phi>
+__device__ __forceinline__ void field_grad(Phi phi, int nx, int ny, int nz, int wall_axis, int x,
+                                           int y, int z, float (&g)[3]) {
+    g[0] = axis_diff([&](int j) { return phi(((int64_t)z * ny + y) * nx + j); }, x, nx,
+                     wall_axis == 0);
+    g[1] = axis_diff([&](int j) { return phi(((int64_t)z * ny + j) * nx + x); }, y, ny,
+                     wall_axis == 1);
+    g[2] = DIM == 3 ? axis_diff([&](int j) { return phi(((int64_t)j * ny + y) * nx + x); }, z, nz,
+                                wall_axis == 2)
+                    : 0.0f;
+}
 
 // Collision of one species at one node, given the mixture, its friction
 // vector V and its own moments.  On return P0 holds the new stored rest
@@ -205,17 +245,24 @@ struct SpeciesConst {
 // which enters the collision with the same factor (1 - 1/(2 tau)) as S, so
 // the forcing bracket becomes e.F - u.F + t e.F + kd (t e.Theta - u.Theta)
 //   = (e.F - u.G) + t e.G,   G = F + kd Theta.
+// FRC 2 also subtracts S_p = w [(e.u)(e.P) - c_s^2 u.P]/c_s^4 with
+// P = c_s^2 grad rho_i (so G = F + kd Theta - P) and adds
+// S_rho = w w_i [(e.u_i^eq)(e.grad rho) - c_s^2 u_i^eq.grad rho]/c_s^2, i.e.
+// the bracket gains t_i e.R - u_i^eq.R with t_i = e.u_i^eq/c_s^2 and
+// R = w_i c_s^2 grad rho (w_i = rho_i/rho).
 template <int LAT, int FRC>
 __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const float (&g)[3],
                                                 float rho_i, float dlt_i, const float (&ue_i)[3],
-                                                const Mix& M, const float (&V)[3], float& P0,
+                                                const Mix& M, const float (&V)[3],
+                                                const Grads& D, float& P0,
                                                 float (&F)[Lat<LAT>::Q]) {
     constexpr int Q = Lat<LAT>::Q;
     using L = Lat<LAT>;
     const float c = K.c, ics = K.ics, itau = K.itau, fp = K.fp;
-    float du[3], T[3], Z[3], Fc[3], Gc[3];
-    float udu = 0.0f, uV = 0.0f, uF = 0.0f, uG = 0.0f;
+    float du[3], T[3], Z[3], Fc[3], Gc[3], Ti[3], Rc[3];
+    float udu = 0.0f, uV = 0.0f, uF = 0.0f, uG = 0.0f, uR = 0.0f;
     const float kr = FRC ? K.kd * rho_i : 0.0f;
+    const float wc = FRC == 2 ? rho_i * M.iR * K.cs2 : 0.0f;   // w_i c_s^2
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         du[d] = ue_i[d] - M.U[d];
@@ -227,9 +274,16 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
         Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
         Fc[d] = c * Fd;                         // c_a . Fc = e.F
         if (FRC) {
-            const float Gd = fmaf(kr, V[d], Fd);
+            float Gd = fmaf(kr, V[d], Fd);
+            if (FRC == 2) Gd = fmaf(-K.cs2, D.gi[d], Gd);
             uG = fmaf(M.U[d], Gd, uG);
             Gc[d] = c * Gd;                     // c_a . Gc = e.G
+        }
+        if (FRC == 2) {
+            const float Rd = wc * D.gm[d];
+            uR = fmaf(ue_i[d], Rd, uR);
+            Ti[d] = ics * c * ue_i[d];          // c_a . Ti = t_i
+            Rc[d] = c * Rd;                     // c_a . Rc = e.R
         }
     }
     if (!FRC) uG = uF;
@@ -249,7 +303,9 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
         const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
         const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
         const float eG = FRC ? cdot<LAT>(a, Gc[0], Gc[1], Gc[2]) : eF;
-        const float Sp = fmaf(t, eG, eF - uG);
+        float Sp = fmaf(t, eG, eF - uG);
+        if (FRC == 2)
+            Sp += fmaf(cdot<LAT>(a, Ti[0], Ti[1], Ti[2]), cdot<LAT>(a, Rc[0], Rc[1], Rc[2]), -uR);
         const float h = fmaf(-L::w(a), dlt_i, F[a]);   // f_a - w_a rho
         // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
         // rounded coefficients of the latter do not sum to exactly 1, which
@@ -271,7 +327,7 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
 // false if a result is not finite.
 template <int LAT, int NS, int FRC>
 __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
-                                        const CollConst& C) {
+                                        const CollConst& C, const float (&gi)[NS][3]) {
     float rho[NS], dlt[NS], ue[NS][3];
 #pragma unroll
     for (int s = 0; s < NS; ++s) species_moments<LAT>(P0[s], F[s], C.c[s], C.g, rho[s], dlt[s], ue[s]);
@@ -283,8 +339,17 @@ __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>
     for (int i = 0; i < NS; ++i) {
         float V[3];
         friction<NS>(i, rho, ue, y, M.iR, V);
-        const SpeciesConst K{C.c[i], C.inv_cs2[i], C.inv_tau[i], C.fpref[i], C.kdiff[i]};
-        ok = collide_species<LAT, FRC>(K, C.g, rho[i], dlt[i], ue[i], M, V, P0[i], F[i]) && ok;
+        const SpeciesConst K{C.c[i], C.inv_cs2[i], C.inv_tau[i], C.fpref[i], C.kdiff[i],
+                             C.cs2[i]};
+        Grads D;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            D.gi[d] = gi[i][d];
+            D.gm[d] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) D.gm[d] += gi[s][d];
+        }
+        ok = collide_species<LAT, FRC>(K, C.g, rho[i], dlt[i], ue[i], M, V, D, P0[i], F[i]) && ok;
     }
     return ok;
 }

@@ -18,14 +18,15 @@ struct LatParams {
     int32_t wall_axis;             // -1: periodic everywhere; 0/1/2: walls at both ends
     int32_t n_species;
     int32_t tile_begin, tile_end;  // this lattice's range in the tile list
-    int32_t forcing;               // 0: standard forcing term; 1: plus S_diff
+    int32_t forcing;               // 0: standard forcing term; 1: plus S_diff; 2: full
     float lam[MAXS][3];            // (lambda_-1, lambda_0, lambda_+1) at Courant +c_s;
                                    // the three floats sum to exactly 1
     float c[MAXS];                 // c_s = sqrt(M_1/M_s)
     float inv_cs2[MAXS];           // 1/c_{s,s}^2 = 3/c_s^2
     float inv_tau[MAXS];           // 1/tau_s
     float fpref[MAXS];             // 1 - 1/(2 tau_s)
-    float kdiff[MAXS];             // 1/(2 tau_s - 1), the weight of S_diff (forcing 1), else 0
+    float kdiff[MAXS];             // 1/(2 tau_s - 1), the weight of S_diff (forcing >= 1), else 0
+    float cs2[MAXS];               // c_{s,s}^2 = c_s^2/3
     float invM[MAXS];              // 1/M_s (normalised masses, M_1 = 1)
     float M[MAXS];                 // normalised masses
     float K[MAXS][MAXS];           // 2 M_i M_j D_ij / (M_1 c_{s,1}^2) = 6 M_i M_j D_ij
@@ -54,7 +55,10 @@ struct Launch {
     int32_t grid;        // work-groups launched (== ntiles when not persistent)
     int32_t bx, by;      // work-group shape (columns)
     int32_t split;       // 0: one thread per column, all species; 1: one wave per species
-    int32_t forcing;     // 0: standard forcing term; 1: plus S_diff (same for every lattice)
+    int32_t forcing;     // 0: standard forcing term; 1: plus S_diff; 2: minus S_p plus S_rho
+                         // plus S_diff (same for every lattice)
+    float* dens;         // forcing 2: species densities of the streamed populations, dense
+                         // node fields [lattice][N][nodes] (written by the pre-pass)
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };

@@ -112,8 +112,13 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         if (q.lattice == LBM_MC_D2Q9 && q.g[2] != 0.0)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: g[2] must be 0 in 2-D", l);
         if (!std::isfinite(q.n0)) return fail(LBM_MC_ERR_INVALID, "lattice %d: n0 not finite", l);
-        if (q.forcing != 0 && q.forcing != 1)
-            return fail(LBM_MC_ERR_INVALID, "lattice %d: forcing must be 0 or 1", l);
+        if (q.forcing < 0 || q.forcing > 2)
+            return fail(LBM_MC_ERR_INVALID, "lattice %d: forcing must be 0, 1 or 2", l);
+        if (q.forcing == 2)
+            for (int a = 0; a < 3; ++a)
+                if (q.bc[a] == LBM_MC_WALL && (a == 0 ? q.nx : (a == 1 ? q.ny : q.nz)) < 3)
+                    return fail(LBM_MC_ERR_INVALID,
+                                "lattice %d: forcing 2 needs >= 3 nodes on the wall axis", l);
         if (q.forcing != p[0].forcing)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: every lattice needs the same forcing", l);
         if (q.reserved != 0) return fail(LBM_MC_ERR_INVALID, "lattice %d: reserved must be 0", l);
@@ -304,6 +309,7 @@ struct Layout {
     std::vector<int64_t> base, field;
     std::vector<int32_t> pitch;
     int64_t total = 0;
+    int64_t nodes_total = 0;   // fluid nodes of all lattices (dense node fields)
 };
 
 Layout make_layout(const lbm_mc_params* p, int32_t L) {
@@ -319,6 +325,7 @@ Layout make_layout(const lbm_mc_params* p, int32_t L) {
         lo.total = round_up(lo.total + plane * q.n_species * q_of(q.lattice), kBaseAlign);
         fb += (int64_t)q.nx * q.ny * q.nz;
     }
+    lo.nodes_total = fb;
     return lo;
 }
 
@@ -355,6 +362,7 @@ struct lbm_mc_ctx {
     double* dpartial = nullptr;
     size_t dpartial_cap = 0;
     double* dtotals = nullptr;
+    float* dens = nullptr;              // forcing 2: densities of the streamed populations
     int one_launch = 1;
     int cus = 256;
     // captured step graphs (index: cur == bufA)
@@ -521,6 +529,7 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.by = c->tune.by;
     L.split = c->tune.split;
     L.forcing = c->params[0].forcing;
+    L.dens = c->dens;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -772,7 +781,8 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
                 P.inv_cs2[i] = (float)(1.0 / nm.cs2[i]);
                 P.inv_tau[i] = (float)(1.0 / nm.tau[i]);
                 P.fpref[i] = (float)(1.0 - 0.5 / nm.tau[i]);
-                P.kdiff[i] = q.forcing == 1 ? (float)(1.0 / (2.0 * nm.tau[i] - 1.0)) : 0.0f;
+                P.kdiff[i] = q.forcing >= 1 ? (float)(1.0 / (2.0 * nm.tau[i] - 1.0)) : 0.0f;
+                P.cs2[i] = (float)nm.cs2[i];
                 P.invM[i] = (float)(1.0 / nm.M[i]);
                 P.M[i] = (float)nm.M[i];
                 for (int j = 0; j < nm.N; ++j) {
@@ -787,7 +797,9 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
     }
     if (hipMalloc(&c->dlp, n_lattices * sizeof(LatParams)) != hipSuccess ||
         hipMalloc(&c->dflag, sizeof(unsigned)) != hipSuccess ||
-        hipMalloc(&c->dtotals, (size_t)n_lattices * (c->N + 3) * sizeof(double)) != hipSuccess)
+        hipMalloc(&c->dtotals, (size_t)n_lattices * (c->N + 3) * sizeof(double)) != hipSuccess ||
+        (p[0].forcing == 2 &&
+         hipMalloc(&c->dens, (size_t)lo.nodes_total * c->N * sizeof(float)) != hipSuccess))
         return bail(fail(LBM_MC_ERR_HIP, "device allocation failed"));
     if (hipMemsetAsync(c->dflag, 0, sizeof(unsigned), c->stream) != hipSuccess)
         return bail(fail(LBM_MC_ERR_HIP, "memset failed"));
@@ -1039,6 +1051,7 @@ lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
     hipFree(c->dtiles);
     hipFree(c->dpartial);
     hipFree(c->dtotals);
+    hipFree(c->dens);
     hipFree(c->dmu);
     hipFree(c->dgpart);
     hipFree(c->dlam);

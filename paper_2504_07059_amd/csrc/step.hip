@@ -23,15 +23,35 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
     t1 = (int)((int64_t)(vb + 1) * ntiles / G);
 }
 
+// Density gradients of every species at node (x, y, layer m) from the dense
+// density fields of one lattice (FRC 2).
+template <int LAT, int NS>
+__device__ __forceinline__ void species_grads(const float* dens, const LatParams& P, int x, int y,
+                                              int m, float (&gi)[NS][3]) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const float* f = dens + s * nodes;
+        field_grad<DIM>([&](int64_t j) { return f[j]; }, P.nx, P.ny, P.nz, P.wall_axis, x,
+                        DIM == 2 ? m : y, DIM == 2 ? 0 : m, gi[s]);
+    }
+}
+
 template <int LAT, int NS, int FRC>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
     CollConst C;
     bool bad;
-    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int,
+    const float* dens;      // FRC 2: this lattice's density fields
+    const LatParams* P;
+    int x, y;
+    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned own) {
-        if (!collide<LAT, NS, FRC>(P0, F, C)) bad = true;
+        float gi[NS][3] = {};
+        if constexpr (FRC == 2) species_grads<LAT, NS>(dens, *P, x, y, m, gi);
+        if (!collide<LAT, NS, FRC>(P0, F, C, gi)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             stb(D, s * Q, own, P0[s]);
@@ -45,6 +65,7 @@ template <int LAT, int NS, int FRC>
 __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
                                               const LatParams* __restrict__ lps,
                                               const Tile* __restrict__ tiles, int ntiles,
+                                              const float* __restrict__ dens,
                                               unsigned* __restrict__ flag) {
     constexpr int DIM = Lat<LAT>::DIM;
     int t0, t1;
@@ -58,7 +79,8 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false};
+        StepOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
+                                FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y};
         march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
@@ -80,14 +102,35 @@ struct SplitOp {
     CollConst C;
     SpeciesConst K;
     float4 (*xch)[NS][64];   // [2][NS][64] exchange buffers in LDS
+    float4 (*xgr)[NS][64];   // FRC 2: [2][NS][64] exchange of the density gradients
     int s, lane;
     bool inside, bad;
+    const float* dens;       // FRC 2: this species' density field
+    const LatParams* P;
+    int x, y;
     __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int m, unsigned own) {
+        constexpr int DIM = Lat<LAT>::DIM;
         float rho_s, dlt_s, ue_s[3];
         species_moments<LAT>(P0, F, K.c, C.g, rho_s, dlt_s, ue_s);
         float4 (*X)[64] = xch[m & 1];
         X[s][lane] = make_float4(rho_s, ue_s[0], ue_s[1], ue_s[2]);
+        Grads gd{};
+        if constexpr (FRC == 2) {
+            const float* f = dens;
+            field_grad<DIM>([&](int64_t j) { return f[j]; }, P->nx, P->ny, P->nz, P->wall_axis,
+                            x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, gd.gi);
+            xgr[m & 1][s][lane] = make_float4(gd.gi[0], gd.gi[1], gd.gi[2], 0.0f);
+        }
         __syncthreads();
+        if constexpr (FRC == 2) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const float4 v = xgr[m & 1][j][lane];
+                gd.gm[0] += v.x;
+                gd.gm[1] += v.y;
+                gd.gm[2] += v.z;
+            }
+        }
         float rho[NS], ue[NS][3];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
@@ -107,7 +150,7 @@ struct SplitOp {
             if (i != s) continue;
             friction<NS>(i, rho, ue, y, M.iR, V);
         }
-        const bool ok = collide_species<LAT, FRC>(K, C.g, rho_s, dlt_s, ue_s, M, V, P0, F) &&
+        const bool ok = collide_species<LAT, FRC>(K, C.g, rho_s, dlt_s, ue_s, M, V, gd, P0, F) &&
                         isfinite(M.R);
         if (inside) {
             stb(D, s * Q, own, P0);
@@ -123,10 +166,12 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
                                                     float* __restrict__ dst,
                                                     const LatParams* __restrict__ lps,
                                                     const Tile* __restrict__ tiles, int ntiles,
-                                                    int bx, unsigned* __restrict__ flag) {
+                                                    int bx, const float* __restrict__ dens,
+                                                    unsigned* __restrict__ flag) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
     __shared__ float4 xch[2][NS][64];
+    __shared__ float4 xgr[2][NS][FRC == 2 ? 64 : 1];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     int t0, t1;
@@ -147,14 +192,116 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
         SplitOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
-                                              P.kdiff[s]},
-                            xch, s, lane, inside, false};
+                                              P.kdiff[s], P.cs2[s]},
+                                 xch, reinterpret_cast<float4 (*)[NS][64]>(xgr), s, lane,
+                                 inside, false,
+                                 FRC == 2 ? dens + P.field_base * NS
+                                                + s * ((int64_t)P.nx * P.ny * P.nz)
+                                          : nullptr,
+                                 &P, x, y};
         march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
                     T.m1, op);
         bad = bad || op.bad;
         __syncthreads();   // the next tile reuses the exchange buffers
     }
     if (bad) atomicOr(flag, 1u);
+}
+
+// ------------------------------------------------- density pre-pass (FRC 2)
+// The pressure and density forcing contributions need density gradients at
+// the time level of the collision, i.e. the densities of the streamed
+// populations at the neighbours.  This pass streams every node (the same
+// gather as the fused step) and stores rho_s = P0/w_0 + sum_a F_a into dense
+// node fields [N][nodes]; the fused step then reads the neighbours' values.
+template <int LAT>
+__device__ __forceinline__ float streamed_density(float P0, const float (&F)[Lat<LAT>::Q]) {
+    float sf = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Lat<LAT>::Q; ++a) sf += F[a];
+    return fmaf(P0, Lat<LAT>::inv_w0, sf);
+}
+
+template <int LAT>
+__device__ __forceinline__ int64_t dense_node(const LatParams& P, int x, int y, int m) {
+    return Lat<LAT>::DIM == 2 ? (int64_t)m * P.nx + x : ((int64_t)m * P.ny + y) * P.nx + x;
+}
+
+template <int LAT, int NS>
+struct DensOp {
+    static constexpr int Q = Lat<LAT>::Q;
+    float* out;
+    const LatParams* P;
+    int64_t nodes;
+    int x, y;
+    __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
+                                               unsigned) {
+        const int64_t node = dense_node<LAT>(*P, x, y, m);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) out[s * nodes + node] = streamed_density<LAT>(P0[s], F[s]);
+    }
+};
+
+template <int LAT>
+struct DensOp1 {
+    static constexpr int Q = Lat<LAT>::Q;
+    float* out;               // this species' field
+    const LatParams* P;
+    int x, y;
+    bool inside;
+    __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int m, unsigned) {
+        const float r = streamed_density<LAT>(P0, F);
+        if (inside) out[dense_node<LAT>(*P, x, y, m)] = r;
+    }
+};
+
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_density(const float* __restrict__ src,
+                                                 const LatParams* __restrict__ lps,
+                                                 const Tile* __restrict__ tiles, int ntiles,
+                                                 float* __restrict__ dens) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    int t0, t1;
+    tile_range(ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = tiles[t];
+        const LatParams& P = lps[T.lat];
+        const int x = T.x0 + (int)threadIdx.x;
+        const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+        if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
+        const GatherConst G = gather_const(P, DIM);
+        const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+        DensOp<LAT, NS> op{dens + P.field_base * NS, &P, nodes, x, y};
+        march<LAT, NS>(make_buf(src + P.base, P.plane * NS * Lat<LAT>::Q, P.plane), G, x, y,
+                       T.m0, T.m1, op);
+    }
+}
+
+// species-split form: block (64, NS), wave s streams species s
+template <int LAT, int NS>
+__global__ void __launch_bounds__(256) k_density_split(const float* __restrict__ src,
+                                                       const LatParams* __restrict__ lps,
+                                                       const Tile* __restrict__ tiles,
+                                                       int ntiles, int bx,
+                                                       float* __restrict__ dens) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    constexpr int Q = Lat<LAT>::Q;
+    const int lane = (int)threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    int t0, t1;
+    tile_range(ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const Tile T = tiles[t];
+        const LatParams& P = lps[T.lat];
+        int x, y;
+        bool zero;
+        const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
+        const GatherConst G = gather_const(P, DIM);
+        const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+        const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
+        DensOp1<LAT> op{dens + P.field_base * NS + s * nodes, &P, x, y, inside};
+        march1<LAT>(make_buf(src + P.base, P.plane * NS * Q, P.plane), G, s, L, x, y, zero,
+                    bx == 64, T.m0, T.m1, op);
+    }
 }
 
 // Initial state of one lattice: f(0) = [1 + e.u_i0/c_s^2] omega rho_i with
@@ -206,7 +353,17 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
             for (int a = 1; a < Q; ++a) f0_out[(int64_t)(s * Q + a) * P.plane + own] = F[s][a];
         }
         // f(0) as gather output: P0 and F_a = f_a - w_a r* = g_a
-        if (!collide<LAT, NS, FRC>(P0, F, C)) bad = true;
+        float gi[NS][3] = {};
+        if constexpr (FRC == 2) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double sc = (double)P.M[s] * (double)P.n0;
+                const double* xs = xl + s * nodes;
+                field_grad<Lat<LAT>::DIM>([&](int64_t j) { return (float)(xs[j] * sc); }, P.nx,
+                                          P.ny, P.nz, P.wall_axis, x, y, z, gi[s]);
+            }
+        }
+        if (!collide<LAT, NS, FRC>(P0, F, C, gi)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             ft_out[(int64_t)(s * Q) * P.plane + own] = P0[s];
@@ -353,6 +510,7 @@ static hipError_t by_shape(int lattice, int ns, int frc, Fn&& fn) {
     auto with_frc = [&](auto lat, auto n) -> hipError_t {
         if (frc == 0) return fn(lat, n, integral_constant<int, 0>{});
         if (frc == 1) return fn(lat, n, integral_constant<int, 1>{});
+        if (frc == 2) return fn(lat, n, integral_constant<int, 2>{});
         return hipErrorInvalidValue;
     };
     auto with_ns = [&](auto lat) -> hipError_t {
@@ -371,12 +529,24 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
     return by_shape(lattice, ns, L.forcing, [&](auto lat, auto n, auto frc) {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value;
+        if (FRC == 2) {
+            if (!L.dens) return hipErrorInvalidValue;
+            if (L.split)
+                hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0,
+                                   L.stream, L.src, L.lp, L.tiles, L.ntiles, L.bx, L.dens);
+            else
+                hipLaunchKernelGGL((k_density<LAT, NS>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                                   L.stream, L.src, L.lp, L.tiles, L.ntiles, L.dens);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         if (L.split)
             hipLaunchKernelGGL((k_step_split<LAT, NS, FRC>), dim3(L.grid), dim3(64, NS), 0,
-                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.flag);
+                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
+                               L.flag);
         else
             hipLaunchKernelGGL((k_step<LAT, NS, FRC>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.flag);
+                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.flag);
         return hipGetLastError();
     });
 }

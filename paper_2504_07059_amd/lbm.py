@@ -17,7 +17,8 @@ LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
 def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
                 walls=(False, False, False), n0=0.0, forcing=0):
     """Fill one lbm_mc_params struct (forcing: 0 or "standard" for the
-    standard forcing term, 1 or "diff" to add the diffusion-driven term)."""
+    standard forcing term, 1 or "diff" to add the diffusion-driven term, 2 or
+    "full" for the whole corrected forcing, - S_p + S_rho + S_diff)."""
     p = Params()
     p.lattice = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}[lattice] if isinstance(lattice, str) \
         else int(lattice)
@@ -34,7 +35,8 @@ def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
     for a in range(3):
         p.g[a] = float(g[a])
     p.n0 = float(n0 or 0.0)
-    p.forcing = {"standard": 0, "diff": 1}[forcing] if isinstance(forcing, str) else int(forcing)
+    p.forcing = {"standard": 0, "diff": 1, "full": 2}[forcing] if isinstance(forcing, str) \
+        else int(forcing)
     p.reserved = 0
     return p
 

@@ -109,16 +109,23 @@ def test_check_rejects_invalid_problems(mutate, status):
 
 
 def test_check_forcing_values():
-    """forcing 0 (standard) and 1 (plus S_diff) are accepted, other values
-    rejected; a batch must share one forcing."""
+    """forcing 0 (standard), 1 (plus S_diff) and 2 (the whole corrected
+    forcing) are accepted, other values rejected; a batch must share one
+    forcing."""
     from paper_2504_07059_amd.lbm import check_problem
-    for forcing, status in ((0, 0), (1, 0), ("diff", 0), (2, 1), (-1, 1)):
+    for forcing, status in ((0, 0), (1, 0), ("diff", 0), (2, 0), ("full", 0), (3, 1), (-1, 1)):
         p = _tube(forcing=forcing)
         st, _, msg = check_problem(p, _x0(p))
         assert st == status, (forcing, msg)
     a, b = _tube(forcing=0), _tube(forcing=1)
     st, _, msg = check_problem([a, b], np.concatenate([_x0(a), _x0(b)]))
     assert st == 1 and "forcing" in msg
+    # the one-sided wall differences of forcing 2 need 3 nodes on the wall axis
+    p = _tube(nx=2, forcing=2)
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 1 and "forcing 2" in msg
+    p = _tube(nx=3, forcing=2)
+    assert check_problem(p, _x0(p))[0] == 0
 
 
 def test_check_rejects_bad_compositions_and_diffusivities():
