@@ -22,7 +22,10 @@ The JSON line also carries
   accuracy:     max |x_s - x_s(oracle)| of the timed run when the oracle result
                 for that step count is stored, and the FP64 mass drift;
   hbm_scale:    the same physics on a 16384 x 1024 tube (3.6 GB per step), where
-                the lattice no longer fits the 256 MB last-level cache;
+                the lattice no longer fits the 256 MB last-level cache; its
+                "variants" time the same tube with the diffusion-driven
+                forcing term (forcing 1), the whole corrected forcing
+                (forcing 2) and a per-node force field;
   batched:      512 independent ternary tubes of uneven sizes (22.8 M nodes),
                 one persistent launch per step against one launch per tube;
   d3q19:        the 3-D layer workload (D3Q19, 4 species, 256 x 128 x 128,
@@ -65,7 +68,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_gpu(w, steps, warmup, autotune=False, tuning=None):
+def time_gpu(w, steps, warmup, autotune=False, tuning=None, accel=None):
     import numpy as np
     import torch
     from paper_2504_07059_amd import lbm
@@ -73,10 +76,10 @@ def time_gpu(w, steps, warmup, autotune=False, tuning=None):
     p = lbm.params_from_workload(w)
     x0 = w.x0()
     if autotune and tuning is None:
-        tmp = lbm.LbmMc(p, x0)
+        tmp = lbm.LbmMc(p, x0, accel=accel)
         tmp.autotune(reps=5)
         tmp.close()
-    sim = lbm.LbmMc(p, x0)
+    sim = lbm.LbmMc(p, x0, accel=accel)
     if tuning is not None:
         sim.set_tuning(*tuning)
     m0 = sim.moments(fields=False)["mass"][0].copy()
@@ -97,6 +100,32 @@ def time_gpu(w, steps, warmup, autotune=False, tuning=None):
     out = sim.moments()
     drift = float(np.abs(out["mass"][0] / m0 - 1).max())
     return sim, out, ms, wall, drift
+
+
+def time_variants(wh, tuning, steps=100, warmup=10):
+    """The HBM-scale workload under the optional physics of the library, at
+    the plain step's execution shape: the diffusion-driven forcing term
+    (forcing 1), the whole corrected forcing (forcing 2: a density pre-pass
+    plus gradients), and a force field k(x) read at every node in place of g
+    (the same values as g, so the physics is the plain step's)."""
+    import dataclasses
+    import torch
+    res = {}
+    for name, w, accel in (
+            ("forcing_1", dataclasses.replace(wh, forcing="diff"), None),
+            ("forcing_2", dataclasses.replace(wh, forcing="full"), None),
+            ("force_field", dataclasses.replace(wh, g=[0.0, 0.0, 0.0]), "field")):
+        if accel == "field":
+            accel = torch.empty((2, wh.nz, wh.ny, wh.nx), dtype=torch.float32, device="cuda")
+            accel[0] = wh.g[0]
+            accel[1] = wh.g[1]
+        sim, out, ms, wall, drift = time_gpu(w, steps, warmup, tuning=tuning, accel=accel)
+        sim.close()
+        res[name] = {"value": wh.nodes * wh.n_species * steps / (ms * 1e3),
+                     "unit": "MLUPS x species", "ms_per_step": ms / steps, "steps": steps,
+                     "mass_drift": drift}
+        del accel
+    return res
 
 
 def accuracy_vs_golden(w, t=20000, tuning=None):
@@ -392,7 +421,7 @@ def main():
             "value": wh.nodes * wh.n_species * wh.steps / (ms2 * 1e3),
             "unit": "MLUPS x species", "ms_per_step": ms2 / wh.steps,
             "roofline": roofline(wh, ms2, wh.steps, t2), "mass_drift": drift2,
-            "tuning": list(t2)}
+            "tuning": list(t2), "variants": time_variants(wh, t2)}
     if not args.no_batched and w.name.startswith("ternary_gravity_1024"):
         line["batched"] = time_batched(200, 20)
     if not args.no_3d and w.name.startswith("ternary_gravity_1024"):

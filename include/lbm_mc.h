@@ -85,7 +85,14 @@ typedef struct lbm_mc_params {
                                <= 0 selects 1/M_max, i.e. a pure heaviest species would
                                have rho = 1 (Sec. 4 opening) */
     int32_t forcing;        /* 0: the standard forcing term (eq. CE_forcing_term_
-                               discretized); other values are rejected */
+                               discretized); 1: plus the diffusion-driven contribution
+                               S_diff of eq. (improved_forcing_scheme); 2: that whole
+                               equation, - S_p + S_rho + S_diff, its density gradients
+                               by central differences of the streamed populations'
+                               densities (one-sided second order next to a wall; a
+                               wall axis needs >= 3 nodes), about 1.5x the step's
+                               traffic.  The same value for every lattice of a batch;
+                               other values are rejected */
     int32_t reserved;       /* must be 0 */
 } lbm_mc_params;
 
@@ -139,6 +146,27 @@ lbm_mc_status lbm_mc_check(const lbm_mc_params* p, int32_t n_lattices, const dou
 lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
                           float* f_a, float* f_b, int64_t buffer_floats, void* hip_stream,
                           lbm_mc_ctx** out);
+
+/*
+ * lbm_mc_init with a position-dependent specific force k(x) in place of the
+ * constant g: F_i = rho_i k(x) for every species, in the force shift of the
+ * equilibrium velocity (eq. first_order_moment_force), the forcing term and
+ * the force-consistent initial velocity u_i0 = -k(x)/2 -- the setting of the
+ * paper's centrifugal case (Sec. 4.2, F_i = rho_i omega_u^2 r).
+ *   accel   device float, caller-owned, borrowed until lbm_mc_destroy (it is
+ *           read by every step, so it must stay valid and may be updated
+ *           between steps): dense node fields [lattice][d][nz][ny][nx],
+ *           d = 2 (D2Q9) or 3 (D3Q19), lattice l starting at
+ *           d * field_offsets[l] (lbm_mc_layout); 4-byte aligned.
+ *   p[l].g  must be 0 for every lattice.
+ * Other arguments as for lbm_mc_init.  Adds about 4 d bytes per node and step
+ * of reads.  The adjoint entry points reject such a context
+ * (LBM_MC_ERR_UNSUPPORTED).  Errors: those of lbm_mc_init, plus
+ * LBM_MC_ERR_INVALID for a NULL or misaligned accel or a nonzero g.
+ */
+lbm_mc_status lbm_mc_init_field(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                                const float* accel, float* f_a, float* f_b,
+                                int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out);
 
 /*
  * Advance every lattice by n_steps time steps (asynchronous).  One step is the

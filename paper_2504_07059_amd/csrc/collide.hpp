@@ -240,16 +240,35 @@ __device__ __forceinline__ void field_grad(Phi phi, int nx, int ny, int nz, int 
 // Collision of one species at one node, given the mixture, its friction
 // vector V and its own moments.  On return P0 holds the new stored rest
 // population and F[a] (a >= 1) the stored deviations g_a.  Returns false if a
-// result is not finite.  FRC 1 adds S_diff: with Theta_i = rho_i V_i,
+// result is not finite.
+//
+// Per direction, with h = f - w rho (the streamed deviation),
+//   f~ - w rho = (1 - 1/tau) h + w E(e),
+//   E(e) = [ (f^(eq) - w rho)/tau + f^(eq)/c_s^2 (e - u).(du/tau - V)
+//            + (1 - 1/(2 tau)) S ] / w,
+// with du = u_i^eq - u; the first term is the BGK relaxation toward f^(0)
+// (eq. feqi0) written as relaxation toward f^(eq) plus its (e - u).du part,
+// the second also carries Omega^ij (eq. Cross_collision_Sirovich).  In the
+// projections t = e.u/c_s^2, q = e.(du/tau - V), e.F, e.G of the direction,
+// E is a cubic polynomial; its even and odd parts
+//   Even = D0 + a2 t^2 + t (ri q + fi e.G)        (+ fi t_i e.R, FRC 2)
+//   Odd  = ra t + b2 q + fi e.F + b3 t^2 q
+// (ri = rho/c_s^2, fi = (1 - 1/(2 tau))/c_s^2; D0, a2 = ra/2, b2, b3 per
+// node) are evaluated once per pair of opposite directions:
+// E(+-e) = Even +- Odd.
+// FRC 1 adds S_diff: with Theta_i = rho_i V_i,
 //   S_diff = w/(2 tau - 1) [(e.u)(e.Theta) - c_s^2 u.Theta]/c_s^4,
-// which enters the collision with the same factor (1 - 1/(2 tau)) as S, so
-// the forcing bracket becomes e.F - u.F + t e.F + kd (t e.Theta - u.Theta)
-//   = (e.F - u.G) + t e.G,   G = F + kd Theta.
+// which enters with the same factor (1 - 1/(2 tau)) as S, so the forcing
+// bracket e.F - u.F + t e.F becomes (e.F - u.G) + t e.G, G = F + kd Theta.
 // FRC 2 also subtracts S_p = w [(e.u)(e.P) - c_s^2 u.P]/c_s^4 with
 // P = c_s^2 grad rho_i (so G = F + kd Theta - P) and adds
 // S_rho = w w_i [(e.u_i^eq)(e.grad rho) - c_s^2 u_i^eq.grad rho]/c_s^2, i.e.
 // the bracket gains t_i e.R - u_i^eq.R with t_i = e.u_i^eq/c_s^2 and
 // R = w_i c_s^2 grad rho (w_i = rho_i/rho).
+// (1 - 1/tau) h is evaluated as fmaf(-1/tau, h, h): one rounding of an exact
+// (1 - 1/tau), so the relaxation keeps f^(eq) as its fixed point; two
+// separately rounded coefficients would scale the equilibrium by a constant
+// factor every step and drift the composition systematically.
 template <int LAT, int FRC>
 __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const float (&g)[3],
                                                 float rho_i, float dlt_i, const float (&ue_i)[3],
@@ -257,63 +276,71 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
                                                 const Grads& D, float& P0,
                                                 float (&F)[Lat<LAT>::Q]) {
     constexpr int Q = Lat<LAT>::Q;
+    constexpr int DIM = Lat<LAT>::DIM;
     using L = Lat<LAT>;
     const float c = K.c, ics = K.ics, itau = K.itau, fp = K.fp;
-    float du[3], T[3], Z[3], Fc[3], Gc[3], Ti[3], Rc[3];
-    float udu = 0.0f, uV = 0.0f, uF = 0.0f, uG = 0.0f, uR = 0.0f;
+    // vectors whose projections on a direction give t, q, e.F, e.G (FRC 2:
+    // t_i, e.R); components beyond DIM are zero and never projected
+    float T[3] = {}, Z[3] = {}, Fc[3] = {}, Gc[3] = {}, Ti[3] = {}, Rc[3] = {};
+    float udu = 0.0f, uV = 0.0f, uG = 0.0f, uR = 0.0f;
     const float kr = FRC ? K.kd * rho_i : 0.0f;
     const float wc = FRC == 2 ? rho_i * M.iR * K.cs2 : 0.0f;   // w_i c_s^2
+    const float cics = c * ics;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        du[d] = ue_i[d] - M.U[d];
+    for (int d = 0; d < DIM; ++d) {
+        const float du = ue_i[d] - M.U[d];
         const float Fd = rho_i * g[d];
-        udu = fmaf(M.U[d], du[d], udu);
+        float Gd = Fd;
+        if (FRC) Gd = fmaf(kr, V[d], Gd);
+        if (FRC == 2) Gd = fmaf(-K.cs2, D.gi[d], Gd);
+        udu = fmaf(M.U[d], du, udu);
         uV = fmaf(M.U[d], V[d], uV);
-        uF = fmaf(M.U[d], Fd, uF);
-        T[d] = ics * c * M.U[d];               // t_a = c_a . T = e.u / c_s^2
-        Z[d] = c * fmaf(itau, du[d], -V[d]);   // c_a . Z = itau e.du - e.V
-        Fc[d] = c * Fd;                         // c_a . Fc = e.F
-        if (FRC) {
-            float Gd = fmaf(kr, V[d], Fd);
-            if (FRC == 2) Gd = fmaf(-K.cs2, D.gi[d], Gd);
-            uG = fmaf(M.U[d], Gd, uG);
-            Gc[d] = c * Gd;                     // c_a . Gc = e.G
-        }
+        uG = fmaf(M.U[d], Gd, uG);
+        T[d] = cics * M.U[d];
+        Z[d] = c * fmaf(itau, du, -V[d]);
+        Fc[d] = c * Fd;
+        Gc[d] = c * Gd;
         if (FRC == 2) {
             const float Rd = wc * D.gm[d];
             uR = fmaf(ue_i[d], Rd, uR);
-            Ti[d] = ics * c * ue_i[d];          // c_a . Ti = t_i
-            Rc[d] = c * Rd;                     // c_a . Rc = e.R
+            Ti[d] = cics * ue_i[d];
+            Rc[d] = c * Rd;
         }
     }
-    if (!FRC) uG = uF;
-    const float b0 = -0.5f * M.uu * ics;
-    const float z0 = fmaf(itau, udu, -uV);
+    const float b0 = -0.5f * M.uu * ics;            // f^(eq)/(w rho) - 1 - t - t^2/2
+    const float z0 = fmaf(itau, udu, -uV);          // u.(du/tau - V)
+    const float ri = rho_i * ics;
+    const float fi = fp * ics;
+    const float B = 1.0f + b0;
+    const float ra = rho_i * fmaf(-ics, z0, itau);  // rho (1/tau - z0/c_s^2)
+    const float D0 = fmaf(itau * rho_i, b0, -fmaf(ri * B, z0, fi * (uG + uR)));
+    const float a2 = 0.5f * ra;
+    const float b2 = ri * B;
+    const float b3 = 0.5f * ri;
     float sgt = 0.0f;
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
-        // f^(eq) - w rho = w rho [t (1 + t/2) + b0],  t = e.u/c_s^2
-        // f~ - w rho = h + (feqd - h)/tau
-        //            + feq/c_s^2 [ (e.du - u.du)/tau - (e.V - u.V) ]     (f^(0), Omega^ij)
-        //            + (1 - 1/(2 tau)) w/c_s^2 [ e.F - u.G + t e.G ]      (S, S_diff)
-        const float wr = L::w(a) * rho_i;
+        if (a > L::opp(a)) continue;               // one pass per opposite pair
+        const int ab = L::opp(a);
         const float t = cdot<LAT>(a, T[0], T[1], T[2]);
-        const float feqd = wr * fmaf(t, fmaf(0.5f, t, 1.0f), b0);
-        const float A = (wr + feqd) * ics;
-        const float yv = cdot<LAT>(a, Z[0], Z[1], Z[2]) - z0;
+        const float q = cdot<LAT>(a, Z[0], Z[1], Z[2]);
         const float eF = cdot<LAT>(a, Fc[0], Fc[1], Fc[2]);
         const float eG = FRC ? cdot<LAT>(a, Gc[0], Gc[1], Gc[2]) : eF;
-        float Sp = fmaf(t, eG, eF - uG);
+        const float t2 = t * t;
+        float ev = fmaf(t2, a2, fmaf(t, fmaf(ri, q, fi * eG), D0));
         if (FRC == 2)
-            Sp += fmaf(cdot<LAT>(a, Ti[0], Ti[1], Ti[2]), cdot<LAT>(a, Rc[0], Rc[1], Rc[2]), -uR);
-        const float h = fmaf(-L::w(a), dlt_i, F[a]);   // f_a - w_a rho
-        // h + (feqd - h)/tau rather than (1 - 1/tau) h + feqd/tau: the two
-        // rounded coefficients of the latter do not sum to exactly 1, which
-        // scales the equilibrium by a constant factor every step and drifts
-        // the composition systematically
-        const float gt = fmaf(itau, feqd - h, h) + fmaf(A, yv, (fp * ics * L::w(a)) * Sp);
-        F[a] = gt;
-        sgt += gt;
+            ev = fmaf(fi * cdot<LAT>(a, Ti[0], Ti[1], Ti[2]), cdot<LAT>(a, Rc[0], Rc[1], Rc[2]),
+                      ev);
+        const float od = fmaf(t, ra, fmaf(q, fmaf(t2, b3, b2), fi * eF));
+        const float w = L::w(a);
+        const float we = w * ev, wo = w * od;
+        const float ha = fmaf(-w, dlt_i, F[a]);
+        const float hb = fmaf(-w, dlt_i, F[ab]);
+        const float ga = fmaf(-itau, ha, ha) + (we + wo);
+        const float gb = fmaf(-itau, hb, hb) + (we - wo);
+        F[a] = ga;
+        F[ab] = gb;
+        sgt += ga + gb;
     }
     float e;
     P0 = store_transform<LAT>(P0, dlt_i, sgt, e);
@@ -322,15 +349,17 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
     return isfinite(sgt) && isfinite(P0);
 }
 
-// Collision of one node, all species.  On return P0[s] holds the new stored
-// rest population and F[s][a] (a >= 1) the stored deviations g_a.  Returns
-// false if a result is not finite.
+// Collision of one node, all species, under the specific force g (the
+// constant one or the node's value of a force field).  On return P0[s] holds
+// the new stored rest population and F[s][a] (a >= 1) the stored deviations
+// g_a.  Returns false if a result is not finite.
 template <int LAT, int NS, int FRC>
 __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
-                                        const CollConst& C, const float (&gi)[NS][3]) {
+                                        const CollConst& C, const float (&g)[3],
+                                        const float (&gi)[NS][3]) {
     float rho[NS], dlt[NS], ue[NS][3];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) species_moments<LAT>(P0[s], F[s], C.c[s], C.g, rho[s], dlt[s], ue[s]);
+    for (int s = 0; s < NS; ++s) species_moments<LAT>(P0[s], F[s], C.c[s], g, rho[s], dlt[s], ue[s]);
     const Mix M = mixture<NS>(rho, ue, C);
     float y[NS][NS];
     tau_solve<NS>(rho, M.R, M.n, C, y);
@@ -349,7 +378,7 @@ __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>
 #pragma unroll
             for (int s = 0; s < NS; ++s) D.gm[d] += gi[s][d];
         }
-        ok = collide_species<LAT, FRC>(K, C.g, rho[i], dlt[i], ue[i], M, V, D, P0[i], F[i]) && ok;
+        ok = collide_species<LAT, FRC>(K, g, rho[i], dlt[i], ue[i], M, V, D, P0[i], F[i]) && ok;
     }
     return ok;
 }

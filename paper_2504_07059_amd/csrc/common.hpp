@@ -59,6 +59,8 @@ struct Launch {
                          // plus S_diff (same for every lattice)
     float* dens;         // forcing 2: species densities of the streamed populations, dense
                          // node fields [lattice][N][nodes] (written by the pre-pass)
+    const float* accel;  // force field k(x), dense node fields [lattice][d][nodes], or null
+                         // (the constant g of each lattice)
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };
@@ -66,8 +68,8 @@ struct Launch {
 // Kernel launchers (defined in the .hip translation units).
 hipError_t launch_step(int lattice, int nspecies, const Launch& L);
 hipError_t launch_init(int lattice, int nspecies, const LatParams* lp_dev, int lat,
-                       const LatParams& lp_host, const double* x0_dev, float* f0_out,
-                       float* ft_out, unsigned* flag, hipStream_t s);
+                       const LatParams& lp_host, const double* x0_dev, const float* accel,
+                       float* f0_out, float* ft_out, unsigned* flag, hipStream_t s);
 hipError_t launch_moments(int lattice, int nspecies, const Launch& L, int direct, float* rho,
                           float* x, float* u, double* partial, int nq);
 hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,

@@ -363,6 +363,7 @@ struct lbm_mc_ctx {
     size_t dpartial_cap = 0;
     double* dtotals = nullptr;
     float* dens = nullptr;              // forcing 2: densities of the streamed populations
+    const float* accel = nullptr;       // caller's force field (lbm_mc_init_field), borrowed
     int one_launch = 1;
     int cus = 256;
     // captured step graphs (index: cur == bufA)
@@ -530,6 +531,7 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.split = c->tune.split;
     L.forcing = c->params[0].forcing;
     L.dens = c->dens;
+    L.accel = c->accel;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -625,6 +627,8 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
     if (c->L != 1) return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: batched contexts are not supported");
     if (c->params[0].forcing != 0)
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: only forcing = 0 is differentiated");
+    if (c->accel)
+        return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: a force-field context is not differentiated");
     const size_t bytes = (size_t)c->layout.total * sizeof(float);
     if (!c->dmu) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
@@ -713,12 +717,21 @@ lbm_mc_status lbm_mc_check(const lbm_mc_params* p, int32_t n_lattices, const dou
     return validate_x0_and_stability(p, n_lattices, x0, lambda_max);
 }
 
-lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const double* x0, float* f_a,
-                          float* f_b, int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out) {
+static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                               const float* accel, float* f_a, float* f_b,
+                               int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out) {
     if (!out) return fail(LBM_MC_ERR_INVALID, "out is NULL");
     *out = nullptr;
     lbm_mc_status st = lbm_mc_check(p, n_lattices, x0, nullptr);
     if (st != LBM_MC_OK) return st;
+    if (accel) {
+        if ((uintptr_t)accel % 4)
+            return fail(LBM_MC_ERR_INVALID, "the force field must be 4-byte aligned");
+        for (int l = 0; l < n_lattices; ++l)
+            if (p[l].g[0] != 0.0 || p[l].g[1] != 0.0 || p[l].g[2] != 0.0)
+                return fail(LBM_MC_ERR_INVALID,
+                            "lattice %d: g must be 0 when a force field is given", l);
+    }
     if (!f_a || !f_b) return fail(LBM_MC_ERR_INVALID, "population buffers must not be NULL");
     if (f_a == f_b) return fail(LBM_MC_ERR_INVALID, "f_a and f_b must be distinct buffers");
     Layout lo = make_layout(p, n_lattices);
@@ -739,6 +752,7 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
     c->Q = q_of(c->lattice);
     c->DIM = dim_of(c->lattice);
     c->params.assign(p, p + n_lattices);
+    c->accel = accel;
     c->layout = lo;
     c->bufA = f_a;
     c->bufB = f_b;
@@ -823,8 +837,8 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
         return bail(fail(LBM_MC_ERR_HIP, "x0 staging allocation failed"));
     hipError_t e = hipMemcpyAsync(dx0, x0, nx0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
     for (int l = 0; l < n_lattices && e == hipSuccess; ++l)
-        e = launch_init(c->lattice, c->N, c->dlp, l, c->hlp[l], dx0, c->prev, c->cur, c->dflag,
-                        c->stream);
+        e = launch_init(c->lattice, c->N, c->dlp, l, c->hlp[l], dx0, accel, c->prev, c->cur,
+                        c->dflag, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (n_lattices == 1)
         c->dx0 = dx0;
@@ -837,6 +851,21 @@ lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const doub
     if (st != LBM_MC_OK) return bail(st);
     *out = c;
     return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_init(const lbm_mc_params* p, int32_t n_lattices, const double* x0, float* f_a,
+                          float* f_b, int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out) {
+    return init_impl(p, n_lattices, x0, nullptr, f_a, f_b, buffer_floats, hip_stream, out);
+}
+
+lbm_mc_status lbm_mc_init_field(const lbm_mc_params* p, int32_t n_lattices, const double* x0,
+                                const float* accel, float* f_a, float* f_b,
+                                int64_t buffer_floats, void* hip_stream, lbm_mc_ctx** out) {
+    if (!accel) {
+        if (out) *out = nullptr;
+        return fail(LBM_MC_ERR_INVALID, "accel is NULL");
+    }
+    return init_impl(p, n_lattices, x0, accel, f_a, f_b, buffer_floats, hip_stream, out);
 }
 
 lbm_mc_status lbm_mc_step(lbm_mc_ctx* c, int64_t n) {

@@ -23,6 +23,31 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
     t1 = (int)((int64_t)(vb + 1) * ntiles / G);
 }
 
+// Index of node (x, y, layer m) in the dense node fields of a lattice.
+template <int LAT>
+__device__ __forceinline__ int64_t dense_node(const LatParams& P, int x, int y, int m) {
+    return Lat<LAT>::DIM == 2 ? (int64_t)m * P.nx + x : ((int64_t)m * P.ny + y) * P.nx + x;
+}
+
+// Specific force at a node: the constant g, or (KF) the caller's force field
+// k(x), dense node fields [lattice][d][nodes] (d = 2 or 3 components).
+template <int LAT, bool KF>
+__device__ __forceinline__ void node_accel(const float* accel, const LatParams& P, const float* gc,
+                                           int64_t node, float (&g)[3]) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    if constexpr (KF) {
+        const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
+        const float* a = accel + P.field_base * DIM;
+        g[0] = a[node];
+        g[1] = a[nodes + node];
+        g[2] = DIM == 3 ? a[2 * nodes + node] : 0.0f;
+    } else {
+        g[0] = gc[0];
+        g[1] = gc[1];
+        g[2] = gc[2];
+    }
+}
+
 // Density gradients of every species at node (x, y, layer m) from the dense
 // density fields of one lattice (FRC 2).
 template <int LAT, int NS>
@@ -38,7 +63,7 @@ __device__ __forceinline__ void species_grads(const float* dens, const LatParams
     }
 }
 
-template <int LAT, int NS, int FRC>
+template <int LAT, int NS, int FRC, bool KF>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -47,11 +72,14 @@ struct StepOp {
     const float* dens;      // FRC 2: this lattice's density fields
     const LatParams* P;
     int x, y;
+    const float* accel;     // KF: the force field
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned own) {
         float gi[NS][3] = {};
         if constexpr (FRC == 2) species_grads<LAT, NS>(dens, *P, x, y, m, gi);
-        if (!collide<LAT, NS, FRC>(P0, F, C, gi)) bad = true;
+        float g[3];
+        node_accel<LAT, KF>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
+        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             stb(D, s * Q, own, P0[s]);
@@ -61,11 +89,12 @@ struct StepOp {
     }
 };
 
-template <int LAT, int NS, int FRC>
+template <int LAT, int NS, int FRC, bool KF>
 __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
                                               const LatParams* __restrict__ lps,
                                               const Tile* __restrict__ tiles, int ntiles,
                                               const float* __restrict__ dens,
+                                              const float* __restrict__ accel,
                                               unsigned* __restrict__ flag) {
     constexpr int DIM = Lat<LAT>::DIM;
     int t0, t1;
@@ -79,8 +108,9 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
-                                FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y};
+        StepOp<LAT, NS, FRC, KF> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
+                                    FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y,
+                                    accel};
         march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
@@ -95,7 +125,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, so several times more waves fit on a SIMD.
-template <int LAT, int NS, int FRC>
+template <int LAT, int NS, int FRC, bool KF>
 struct SplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -108,10 +138,13 @@ struct SplitOp {
     const float* dens;       // FRC 2: this species' density field
     const LatParams* P;
     int x, y;
+    const float* accel;      // KF: the force field
     __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int m, unsigned own) {
         constexpr int DIM = Lat<LAT>::DIM;
+        float g[3];
+        node_accel<LAT, KF>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
         float rho_s, dlt_s, ue_s[3];
-        species_moments<LAT>(P0, F, K.c, C.g, rho_s, dlt_s, ue_s);
+        species_moments<LAT>(P0, F, K.c, g, rho_s, dlt_s, ue_s);
         float4 (*X)[64] = xch[m & 1];
         X[s][lane] = make_float4(rho_s, ue_s[0], ue_s[1], ue_s[2]);
         Grads gd{};
@@ -150,7 +183,7 @@ struct SplitOp {
             if (i != s) continue;
             friction<NS>(i, rho, ue, y, M.iR, V);
         }
-        const bool ok = collide_species<LAT, FRC>(K, C.g, rho_s, dlt_s, ue_s, M, V, gd, P0, F) &&
+        const bool ok = collide_species<LAT, FRC>(K, g, rho_s, dlt_s, ue_s, M, V, gd, P0, F) &&
                         isfinite(M.R);
         if (inside) {
             stb(D, s * Q, own, P0);
@@ -161,12 +194,13 @@ struct SplitOp {
     }
 };
 
-template <int LAT, int NS, int FRC>
+template <int LAT, int NS, int FRC, bool KF>
 __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
                                                     float* __restrict__ dst,
                                                     const LatParams* __restrict__ lps,
                                                     const Tile* __restrict__ tiles, int ntiles,
                                                     int bx, const float* __restrict__ dens,
+                                                    const float* __restrict__ accel,
                                                     unsigned* __restrict__ flag) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
@@ -190,7 +224,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         // the species' own constants, read with the uniform species index
         // (scalar loads; no run-time indexing of register arrays)
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-        SplitOp<LAT, NS, FRC> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+        SplitOp<LAT, NS, FRC, KF> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
                                               P.kdiff[s], P.cs2[s]},
                                  xch, reinterpret_cast<float4 (*)[NS][64]>(xgr), s, lane,
@@ -198,7 +232,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
                                  FRC == 2 ? dens + P.field_base * NS
                                                 + s * ((int64_t)P.nx * P.ny * P.nz)
                                           : nullptr,
-                                 &P, x, y};
+                                 &P, x, y, accel};
         march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
                     T.m1, op);
         bad = bad || op.bad;
@@ -219,11 +253,6 @@ __device__ __forceinline__ float streamed_density(float P0, const float (&F)[Lat
 #pragma unroll
     for (int a = 1; a < Lat<LAT>::Q; ++a) sf += F[a];
     return fmaf(P0, Lat<LAT>::inv_w0, sf);
-}
-
-template <int LAT>
-__device__ __forceinline__ int64_t dense_node(const LatParams& P, int x, int y, int m) {
-    return Lat<LAT>::DIM == 2 ? (int64_t)m * P.nx + x : ((int64_t)m * P.ny + y) * P.nx + x;
 }
 
 template <int LAT, int NS>
@@ -309,9 +338,10 @@ __global__ void __launch_bounds__(256) k_density_split(const float* __restrict__
 // velocity), rho_i = x_i M_i n0, evaluated in double and stored as
 // P0 = f_0 and g_a = f_a - (w_a/w_0) P0 + w_a (f_0 - P0)/(1 - w_0) in f0_out;
 // then one collision, stored in ft_out.
-template <int LAT, int NS, int FRC>
+template <int LAT, int NS, int FRC, bool KF>
 __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps, int lat,
                                               const double* __restrict__ x0,
+                                              const float* __restrict__ accel,
                                               float* __restrict__ f0_out,
                                               float* __restrict__ ft_out,
                                               unsigned* __restrict__ flag) {
@@ -329,6 +359,8 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
         const int y = (int)(r % P.ny);
         const int z = (int)(r / P.ny);
         const int64_t own = P.base + ((int64_t)z * P.ny + y) * P.pitch + x;
+        float g[3];
+        node_accel<LAT, KF>(accel, P, C.g, id, g);
         float P0[NS], F[NS][Q];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -343,8 +375,8 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
             for (int a = 1; a < Q; ++a) {
                 const double wa = LAT == 0 ? (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0)
                                            : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
-                const double eu = c * (double)cdot<LAT>(a, -0.5f * C.g[0], -0.5f * C.g[1],
-                                                        -0.5f * C.g[2]);
+                const double eu = c * (double)cdot<LAT>(a, -0.5f * g[0], -0.5f * g[1],
+                                                        -0.5f * g[2]);
                 const double fa = wa * rho * (1.0 + ics * eu);
                 F[s][a] = (float)(fa - wa / w0 * (double)p0 + wa * rem);
             }
@@ -363,7 +395,7 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
                                           P.ny, P.nz, P.wall_axis, x, y, z, gi[s]);
             }
         }
-        if (!collide<LAT, NS, FRC>(P0, F, C, gi)) bad = true;
+        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             ft_out[(int64_t)(s * Q) * P.plane + own] = P0[s];
@@ -385,13 +417,21 @@ struct MomOp {
     int64_t nodes;
     int nx, ny, x, y;
     CollConst C;
+    const float* accel;      // this lattice's force field, or null (constant g)
     double acc[NS + 3];
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned) {
+        const int64_t node = DIM == 2 ? (int64_t)m * nx + x : ((int64_t)m * ny + y) * nx + x;
+        float g[3] = {C.g[0], C.g[1], C.g[2]};
+        if (accel) {
+            g[0] = accel[node];
+            g[1] = accel[nodes + node];
+            g[2] = DIM == 3 ? accel[2 * nodes + node] : 0.0f;
+        }
         float rho[NS], dlt[NS], ue[NS][3];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            species_moments<LAT>(P0[s], F[s], C.c[s], C.g, rho[s], dlt[s], ue[s]);
+            species_moments<LAT>(P0[s], F[s], C.c[s], g, rho[s], dlt[s], ue[s]);
         float R = 0.0f, n = 0.0f, U[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -401,7 +441,6 @@ struct MomOp {
             for (int d = 0; d < 3; ++d) U[d] = fmaf(rho[s], ue[s][d], U[d]);
         }
         const float iR = 1.0f / R;
-        const int64_t node = DIM == 2 ? (int64_t)m * nx + x : ((int64_t)m * ny + y) * nx + x;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (rho_out) rho_out[s * nodes + node] = rho[s];
@@ -420,6 +459,7 @@ template <int LAT, int NS>
 __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
                                                  const LatParams* __restrict__ lps,
                                                  const Tile* __restrict__ tiles, int direct,
+                                                 const float* __restrict__ accel,
                                                  float* rho, float* xo, float* u,
                                                  double* __restrict__ partial, int nq) {
     constexpr int Q = Lat<LAT>::Q;
@@ -438,6 +478,7 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
     op.nodes = nodes;
     op.nx = P.nx; op.ny = P.ny; op.x = x; op.y = y;
     op.C = coll_const(P);
+    op.accel = accel ? accel + P.field_base * DIM : nullptr;
 #pragma unroll
     for (int q = 0; q < NS + 3; ++q) op.acc[q] = 0.0;
     if (x < P.nx && (DIM == 2 || y < P.ny)) {
@@ -502,15 +543,19 @@ __global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lp
 }
 
 // ---------------------------------------------------------------- launchers
-// Calls fn(lattice, species count, forcing) with the three as compile-time
-// constants.
+// Calls fn(lattice, species count, forcing, force field) with the four as
+// compile-time constants.
 template <typename Fn>
-static hipError_t by_shape(int lattice, int ns, int frc, Fn&& fn) {
+static hipError_t by_shape(int lattice, int ns, int frc, bool kf, Fn&& fn) {
     using std::integral_constant;
+    auto with_kf = [&](auto lat, auto n, auto f) -> hipError_t {
+        if (kf) return fn(lat, n, f, integral_constant<bool, true>{});
+        return fn(lat, n, f, integral_constant<bool, false>{});
+    };
     auto with_frc = [&](auto lat, auto n) -> hipError_t {
-        if (frc == 0) return fn(lat, n, integral_constant<int, 0>{});
-        if (frc == 1) return fn(lat, n, integral_constant<int, 1>{});
-        if (frc == 2) return fn(lat, n, integral_constant<int, 2>{});
+        if (frc == 0) return with_kf(lat, n, integral_constant<int, 0>{});
+        if (frc == 1) return with_kf(lat, n, integral_constant<int, 1>{});
+        if (frc == 2) return with_kf(lat, n, integral_constant<int, 2>{});
         return hipErrorInvalidValue;
     };
     auto with_ns = [&](auto lat) -> hipError_t {
@@ -526,11 +571,14 @@ static hipError_t by_shape(int lattice, int ns, int frc, Fn&& fn) {
 
 hipError_t launch_step(int lattice, int ns, const Launch& L) {
     if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
-    return by_shape(lattice, ns, L.forcing, [&](auto lat, auto n, auto frc) {
+    return by_shape(lattice, ns, L.forcing, L.accel != nullptr,
+                    [&](auto lat, auto n, auto frc, auto kf) {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value;
+        constexpr bool KF = decltype(kf)::value;
         if (FRC == 2) {
             if (!L.dens) return hipErrorInvalidValue;
+            // (the force does not enter the densities)
             if (L.split)
                 hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0,
                                    L.stream, L.src, L.lp, L.tiles, L.ntiles, L.bx, L.dens);
@@ -541,25 +589,29 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
             if (e != hipSuccess) return e;
         }
         if (L.split)
-            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC>), dim3(L.grid), dim3(64, NS), 0,
+            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, KF>), dim3(L.grid), dim3(64, NS), 0,
                                L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
-                               L.flag);
+                               L.accel, L.flag);
         else
-            hipLaunchKernelGGL((k_step<LAT, NS, FRC>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.flag);
+            hipLaunchKernelGGL((k_step<LAT, NS, FRC, KF>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.accel,
+                               L.flag);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const LatParams& h,
-                       const double* x0, float* f0, float* ft, unsigned* flag, hipStream_t s) {
+                       const double* x0, const float* accel, float* f0, float* ft,
+                       unsigned* flag, hipStream_t s) {
     const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
     const int64_t blocks = std::min<int64_t>((nodes + 255) / 256, 65536);
-    return by_shape(lattice, ns, h.forcing, [&](auto la, auto n, auto frc) {
+    return by_shape(lattice, ns, h.forcing, accel != nullptr,
+                    [&](auto la, auto n, auto frc, auto kf) {
         constexpr int LAT = decltype(la)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value;
-        hipLaunchKernelGGL((k_init<LAT, NS, FRC>), dim3((unsigned)blocks), dim3(256), 0, s, lp,
-                           lat, x0, f0, ft, flag);
+        constexpr bool KF = decltype(kf)::value;
+        hipLaunchKernelGGL((k_init<LAT, NS, FRC, KF>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           lp, lat, x0, accel, f0, ft, flag);
         return hipGetLastError();
     });
 }
@@ -568,7 +620,7 @@ template <int LAT, int NS>
 static hipError_t launch_moments_t(const Launch& L, int direct, float* rho, float* x, float* u,
                                    double* partial, int nq) {
     hipLaunchKernelGGL((k_moments<LAT, NS>), dim3(L.ntiles), dim3(L.bx, L.by), 0, L.stream, L.src,
-                       L.lp, L.tiles, direct, rho, x, u, partial, nq);
+                       L.lp, L.tiles, direct, L.accel, rho, x, u, partial, nq);
     return hipGetLastError();
 }
 

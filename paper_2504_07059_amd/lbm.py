@@ -80,9 +80,12 @@ class LbmMc:
     """One context of the library over torch-owned population buffers.
 
     params: one Params or a list (batched); x0: float64 array [L*N*nodes]
-    (or any array whose C-order flattening is that)."""
+    (or any array whose C-order flattening is that).  accel: optional force
+    field k(x) replacing g (params' g must be 0), float32 on the device,
+    [d, nz, ny, nx] per lattice concatenated (d = 2 or 3); kept referenced
+    by the context, which reads it every step."""
 
-    def __init__(self, params, x0, device="cuda", stream=None):
+    def __init__(self, params, x0, device="cuda", stream=None, accel=None):
         self._arr, self.L = _arr(params)
         self.params = list(self._arr)
         self.total, self.offsets, self.pitch, self.field_offsets = layout(self.params)
@@ -98,10 +101,20 @@ class LbmMc:
         x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(-1))
         self._x0 = x0
         self.ctx = ctypes.c_void_p()
-        check(lib.lbm_mc_init(self._arr, self.L,
-                              x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              _ptr(self.fa), _ptr(self.fb), self.total,
-                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)))
+        xp = x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        if accel is None:
+            self.accel = None
+            check(lib.lbm_mc_init(self._arr, self.L, xp, _ptr(self.fa), _ptr(self.fb),
+                                  self.total, sp, ctypes.byref(self.ctx)))
+        else:
+            want = self.dim * sum(self.nodes)
+            if accel.dtype != torch.float32 or accel.device != self.fa.device or \
+                    accel.numel() != want:
+                raise ValueError(f"accel must be float32 on {self.fa.device} with {want} values")
+            self.accel = accel.contiguous()
+            check(lib.lbm_mc_init_field(self._arr, self.L, xp, _ptr(self.accel), _ptr(self.fa),
+                                        _ptr(self.fb), self.total, sp, ctypes.byref(self.ctx)))
 
     # ---------------------------------------------------------------- stepping
     def step(self, n=1):

@@ -184,3 +184,27 @@ def test_init_rejects_bad_buffers_before_touching_the_gpu():
     assert st == 1 and b"floats" in L.lib.lbm_mc_last_error()
     assert L.lib.lbm_mc_step(None, 1) == 1
     assert L.lib.lbm_mc_destroy(None) == 0
+
+
+def test_init_field_rejects_bad_arguments_before_touching_the_gpu():
+    """lbm_mc_init_field: a NULL or misaligned force field, or a nonzero g
+    beside it, is rejected before any device work."""
+    L = _lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    ctx = ctypes.c_void_p()
+    p = _tube(g=(0.0, 0.0, 0.0))
+    x = np.ascontiguousarray(_x0(p))
+    arr = (L.Params * 1)(p)
+    st = L.lib.lbm_mc_init_field(arr, 1, x.ctypes.data_as(dp), None, ctypes.c_void_p(4096),
+                                 ctypes.c_void_p(8192), 10 ** 6, None, ctypes.byref(ctx))
+    assert st == 1 and b"accel" in L.lib.lbm_mc_last_error() and not ctx.value
+    st = L.lib.lbm_mc_init_field(arr, 1, x.ctypes.data_as(dp), ctypes.c_void_p(4098),
+                                 ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
+                                 ctypes.byref(ctx))
+    assert st == 1 and b"aligned" in L.lib.lbm_mc_last_error()
+    q = _tube(g=(1e-6, 0.0, 0.0))
+    arr = (L.Params * 1)(q)
+    st = L.lib.lbm_mc_init_field(arr, 1, x.ctypes.data_as(dp), ctypes.c_void_p(1 << 20),
+                                 ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
+                                 ctypes.byref(ctx))
+    assert st == 1 and b"g must be 0" in L.lib.lbm_mc_last_error()

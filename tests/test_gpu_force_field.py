@@ -1,0 +1,210 @@
+"""GPU tests of the position-dependent specific force k(x) (lbm_mc_init_field)
+against the oracle's force-field models, through the C ABI.
+
+Bars as for the constant force: mole fractions within 1e-5 of the oracle,
+per-species mass drift below 1e-6, post-collision populations within 2e-6 of
+the oracle relative to the largest population.  The ultracentrifuge of
+Sec. 4.2 (the paper's numbers) is run from its analytic steady profile and
+compared with the oracle over the same steps and with the profile itself."""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_workloads as W
+from oracle import closed_forms, evd
+from oracle.lattice import DTYPE
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+X_TOL = 1e-5
+MASS_TOL = 1e-6
+F_RTOL = 2e-6
+WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
+           19: [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12}
+
+
+def _lbm():
+    from paper_2504_07059_amd import lbm
+    return lbm
+
+
+def _announce(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+def _field(w, seed, amp):
+    """A smooth seeded force field: three sinusoids per component, float32
+    [d, nz, ny, nx] (d = 2 or 3)."""
+    rng = np.random.default_rng(seed)
+    d = 2 if w.lattice == "D2Q9" else 3
+    zz, yy, xx = np.meshgrid(np.arange(w.nz), np.arange(w.ny), np.arange(w.nx), indexing="ij")
+    out = np.zeros((d, w.nz, w.ny, w.nx))
+    for c in range(d):
+        for _ in range(3):
+            kx, ky, kz = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            out[c] += amp * rng.uniform(-1, 1) * np.sin(
+                2 * np.pi * (kx * xx / w.nx + ky * yy / w.ny + kz * zz / w.nz) + ph)
+    return out.astype(np.float32)
+
+
+def _oracle_field(acc):
+    """[3, nz, ny, nx] float64 from the device field's float32 values."""
+    a = torch.tensor(acc, dtype=DTYPE)
+    if a.shape[0] == 2:
+        a = torch.cat([a, torch.zeros_like(a[:1])])
+    return a
+
+
+def _wk(name, lattice, shape, masses, walls, steps, seed=11, forcing="standard", diff=None):
+    N = len(masses)
+    if diff is None:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(0.06, 0.1, size=(N, N))
+        diff = ((d + d.T) / 2).tolist()
+    return W.Workload(name, lattice, *shape, masses, diff, 1.0, [0.0, 0.0, 0.0], list(walls),
+                      steps, "random", seed=seed, forcing=forcing)
+
+
+# the ternary diffusivities that pass the linear stability check (accepted draw)
+TERNARY = W.pairs_to_matrix(W.load_accepted()["ternary_gravity"]["pairs"], 3)
+CASES = [
+    _wk("d2q9_n3_xwall", "D2Q9", (130, 40, 1), [2.0, 28.0, 44.0], (True, False, False), 24,
+        diff=TERNARY),
+    _wk("d2q9_n2_ywall", "D2Q9", (70, 33, 1), [1.0, 3.0], (False, True, False), 24),
+    _wk("d3q19_n4_zwall", "D3Q19", (40, 21, 19), [1.0, 2.0, 3.0, 4.0], (False, False, True), 16),
+    _wk("d2q9_n3_xwall_full", "D2Q9", (130, 40, 1), [2.0, 28.0, 44.0], (True, False, False), 24,
+        forcing="full", diff=TERNARY),
+]
+
+
+def _shape(w, variant):
+    if variant:
+        return (64, 1, 4, 0, 1) if w.lattice == "D2Q9" else (16, 4, 3, 0, 1)
+    return (64, 1, 4, 0, 0) if w.lattice == "D2Q9" else (16, 4, 3, 0, 0)
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["joint", "split"])
+@pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
+def test_force_field_matches_oracle(w, variant):
+    """A seeded smooth field k(x) (amplitude 3e-5) in place of g: the force
+    shift of u_i^eq, the forcing term and the initial velocity -k/2 all take
+    the node's value; against the oracle with the same field."""
+    _announce(f"force field {w.name} variant {variant}")
+    lbm = _lbm()
+    acc = _field(w, seed=5, amp=3e-5)
+    m = evd.Model(w.lattice, w.nx, w.ny, w.nz, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                  w.tau1, walls=w.walls, force_field=_oracle_field(acc), forcing=w.forcing)
+    f = evd.run(m, evd.initial_populations(m, torch.tensor(w.x0(), dtype=DTYPE)), w.steps)
+    ob = evd.observables(m, f)
+    ft = evd.collide(m, f)
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0(),
+                    accel=torch.tensor(acc, device="cuda"))
+    sim.set_tuning(*_shape(w, variant))
+    m0 = sim.moments(fields=False)["mass"][0].copy()
+    sim.step(w.steps)
+    out = sim.moments()
+    sim.sync()
+    dx = (sim.field(out, "x").double().cpu() - ob["x"]).abs().max().item()
+    fg = sim.populations("cur").double().cpu()
+    df = ((fg - ft).abs().max() / ft.abs().max()).item()
+    drift = np.abs(out["mass"][0] / m0 - 1).max()
+    # the observables' velocity also takes the field (u_i^eq = j/rho + k/2)
+    du = (sim.field(out, "u").double().cpu() - ob["u"].permute(3, 0, 1, 2)[:sim.dim]).abs().max()
+    sim.close()
+    assert dx < X_TOL, dx
+    assert df < F_RTOL, df
+    assert drift < MASS_TOL, drift
+    assert du.item() < 1e-6, du.item()
+
+
+def test_uniform_field_equals_constant_force():
+    """A field equal to g at every node gives exactly the populations of the
+    constant-g context (same arithmetic, the value taken from memory)."""
+    lbm = _lbm()
+    w = dataclasses.replace(CASES[0], g=[2e-5, -1e-5, 0.0])
+    _announce(f"uniform field {w.name}")
+    a = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    w0 = dataclasses.replace(w, g=[0.0, 0.0, 0.0])
+    acc = torch.empty((2, 1, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    acc[0] = 2e-5
+    acc[1] = -1e-5
+    b = lbm.LbmMc(lbm.params_from_workload(w0), w.x0(), accel=acc)
+    a.step(50)
+    b.step(50)
+    pa = a.populations("cur")
+    pb = b.populations("cur")
+    a.sync()
+    b.sync()
+    assert torch.equal(pa, pb)
+    a.close()
+    b.close()
+
+
+def _stored(f, Q):
+    """Stored representation of FP64 populations [N, Q, ...]: P0 = f_0 and
+    g_a = f_a - (w_a/w_0) P0, with the rounded P0."""
+    w = torch.tensor(WEIGHTS[Q], dtype=DTYPE)
+    p0 = f[:, 0].float().double()
+    out = f.clone()
+    out[:, 0] = p0
+    out[:, 1:] = f[:, 1:] - (w[1:] / w[0])[None, :, None, None, None] * p0[:, None]
+    return out.float()
+
+
+def test_ultracentrifuge_matches_oracle_and_stays_on_profile():
+    """Sec. 4.2 with the paper's numbers (binary UF6 isotopes, M1/M2 =
+    0.991481, C = -1.2358e-8, tau_1 = 0.6, D_12 = 0.08, 500 x 3 nodes, walls
+    at the r ends, F_i = rho_i omega_u^2 r).  Started from the analytic steady
+    profile (restored from the oracle's state, since its total mole number
+    varies with r), 2000 steps: mole fractions within 1e-5 of the oracle's
+    run, and the interior (20 nodes from the walls) within 2 % of the
+    profile's own variation of where it started."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        gd = json.load(fh)["ultracentrifuge"]
+    C, ratio = gd["C"], gd["M1_over_M2"]
+    M = [1.0, 1.0 / ratio]
+    omega2 = C * (M[0] / 3.0) / (M[0] - M[1])
+    nx, ny, steps = gd["R_nodes"], gd["H_nodes"], 2000
+    _announce(f"ultracentrifuge {nx}x{ny}, {steps} steps")
+    r = np.arange(nx, dtype=float)
+    xb = np.array([0.5, 0.5])
+    wb = xb * np.array(M) / (xb * np.array(M)).sum()
+    rho = closed_forms.centrifuge_densities(M, wb * nx, r, omega2)
+    n = (rho / np.array(M)[:, None]).sum(0)
+    x = rho / np.array(M)[:, None] / n
+    acc = np.zeros((2, 1, ny, nx), dtype=np.float32)
+    acc[0, 0] = (omega2 * r).astype(np.float32)
+    D = [[0.0, gd["D12"]], [gd["D12"], 0.0]]
+    m = evd.Model("D2Q9", nx, ny, 1, M, torch.tensor(D, dtype=DTYPE), gd["tau1"],
+                  walls=(True, False, False), force_field=_oracle_field(acc))
+    x0 = np.repeat(x[:, None, None, :], ny, axis=2)
+    f0 = evd.initial_populations(m, torch.tensor(x0, dtype=DTYPE))
+    f0 = f0 * torch.tensor(n / m.default_n0(), dtype=DTYPE)[None, None, None, None, :]
+    ft0 = evd.collide(m, f0)
+    f = evd.run(m, f0, steps)
+    x_ref = evd.observables(m, f)["x"][:, 0].numpy()           # [N, ny, nx]
+    lbm = _lbm()
+    p = lbm.make_params("D2Q9", nx, ny, 1, M, D, gd["tau1"], walls=(True, False, False))
+    sim = lbm.LbmMc(p, x0, accel=torch.tensor(acc, device="cuda"))
+    cur = torch.zeros_like(sim.fa)
+    prev = torch.zeros_like(sim.fa)
+    sim.view(cur).copy_(_stored(ft0, 9).cuda())
+    sim.view(prev).copy_(_stored(f0, 9).cuda())
+    sim.restore(cur, prev, 0)
+    out0 = sim.moments()
+    x_a = sim.field(out0, "x").double().cpu().numpy()[:, 0]
+    sim.step(steps)
+    out = sim.moments()
+    sim.sync()
+    x_b = sim.field(out, "x").double().cpu().numpy()[:, 0]
+    sim.close()
+    assert np.abs(x_a[0] - x[0][None, :]).max() < 1e-6
+    assert np.abs(x_b - x_ref).max() < X_TOL
+    variation = x[0].max() - x[0].min()
+    assert np.abs(x_b[0] - x_a[0])[:, 20:-20].max() < 0.02 * variation
