@@ -1028,6 +1028,9 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
         c->tune = t;
         lbm_mc_status st = build_tiles(c);
         if (st != LBM_MC_OK) return st;
+        // a persistent grid no smaller than the tile list is the same launch
+        // as the non-persistent candidate of the same shape
+        if (t.persistent > 0 && t.persistent >= (int)c->htiles.size()) continue;
         for (int i = 0; i < 2; ++i) {
             st = launch_one(c, c->cur, c->prev, c->stream);
             if (st != LBM_MC_OK) return st;
