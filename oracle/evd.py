@@ -37,7 +37,10 @@ Readings taken where the paper is silent (each repeated at its function):
      streamed populations at the same time level, by second-order central
      differences along each lattice axis (periodic axes wrap); at a node next
      to a wall the second-order one-sided difference into the fluid is used
-     (a wall axis then needs at least 3 nodes).
+     (a wall axis then needs at least 3 nodes);
+  R10 the moving-wall term of Appendix A takes rho_i and the mass fraction
+     w_i of the streamed populations at the wall node (the term adds no mass,
+     so they do not depend on it), and a wall moves only along itself.
 """
 import math
 from dataclasses import dataclass, field
@@ -77,6 +80,8 @@ class Model:
     walls: Sequence[bool] = (False, False, False)
     n0: Optional[float] = None
     force_field: Optional[torch.Tensor] = None   # [3, nz, ny, nx] overrides g
+    wall_velocity: Optional[torch.Tensor] = None # [2, 3]: velocity of the wall at the low
+                                                 # and high end of the wall axis (tangential)
     forcing: str = "standard"   # "standard": eq. (CE_forcing_term_discretized);
                                 # "diff": plus S_diff of eq. (improved_forcing_scheme);
                                 # "full": the whole of eq. (improved_forcing_scheme),
@@ -103,6 +108,15 @@ class Model:
                 raise ValueError("a wall axis needs at least 2 nodes")
         if self.lat.dim == 2 and self.walls[2]:
             raise ValueError("no z walls in 2-D")
+        if self.wall_velocity is not None:
+            self.wall_velocity = torch.as_tensor(self.wall_velocity, dtype=DTYPE)
+            ax = [a for a in range(3) if self.walls[a]]
+            if not ax:
+                raise ValueError("a wall velocity needs a wall axis")
+            if bool((self.wall_velocity[:, ax[0]] != 0).any()):
+                raise ValueError("wall velocities must be tangential to the wall")
+            if self.lat.dim == 2 and bool((self.wall_velocity[:, 2] != 0).any()):
+                raise ValueError("no z velocity in 2-D")
         if self.forcing not in ("standard", "diff", "full"):
             raise ValueError("forcing must be 'standard', 'diff' or 'full'")
         if self.forcing == "full":
@@ -472,6 +486,46 @@ def stream(model, ft):
             idx = [slice(None)] * 5
             idx[d] = layer
             out[tuple(idx)] = out[tuple(idx)] + add
+    if model.wall_velocity is not None:
+        out = moving_wall_terms(model, out)
+    return out
+
+
+def moving_wall_terms(model, f):
+    """Moving-wall term of Appendix A (the closing remark on non-stationary
+    walls): at a node O next to a wall moving with tangential velocity u_w,
+    every direction alpha pointing away from the wall gains
+        + 2 omega_alpha rho_i w_i (e^i_alpha . u_w) / c_{s,i}^2,
+    the paper's -2 omega rho_i w_i (e_alphabar . u_w)/c_s^2 written for the
+    reflected direction (e_alpha = -e_alphabar).  Reading R10: rho_i and the
+    mass fraction w_i = rho_i/rho are those of the streamed populations at O
+    (the term adds no mass, so they are the same before and after it).
+    f: streamed populations after the Appendix A terms."""
+    N, Q = model.N, model.lat.Q
+    e = model.velocities()                                  # [N, Q, 3]
+    cs2 = model.sound2()
+    a = [ax for ax in range(3) if model.walls[ax]][0]
+    d = AXIS_DIM[a]
+    n = model.shape_axis(a)
+    out = f.clone()
+    for side, layer in ((0, 0), (1, n - 1)):
+        uw = model.wall_velocity[side]
+        if not bool((uw != 0).any()):
+            continue
+        sigma = -1 if side == 0 else 1
+        here = f.select(d, layer)                            # [N, Q, ., .]
+        rho_i = here.sum(dim=1)                              # [N, ., .]
+        w_i = rho_i / rho_i.sum(dim=0, keepdim=True)
+        add = torch.zeros_like(here)
+        for i in range(N):
+            for al in range(Q):
+                if sigma * model.lat.dirs[al][a] >= 0:
+                    continue
+                eu = float(e[i, al] @ uw)
+                add[i, al] = 2.0 * float(model.lat.w[al]) * rho_i[i] * w_i[i] * eu / cs2[i]
+        idx = [slice(None)] * 5
+        idx[d] = layer
+        out[tuple(idx)] = out[tuple(idx)] + add
     return out
 
 
