@@ -94,6 +94,13 @@ typedef struct lbm_mc_params {
                                traffic.  The same value for every lattice of a batch;
                                other values are rejected */
     int32_t reserved;       /* must be 0 */
+    double wall_velocity[2][3]; /* velocity of the wall at the low ([0]) and high ([1]) end
+                               of the wall axis, tangential to it (the component along
+                               the wall axis must be 0; all 0 without walls).  A moving
+                               wall adds the term of Appendix A's closing remark,
+                               -2 omega_a rho_i w_i (e_a.u_w)/c_{s,i}^2 for the reflected
+                               direction, with rho_i and the mass fraction w_i of the
+                               streamed populations at the wall node */
 } lbm_mc_params;
 
 typedef struct lbm_mc_ctx lbm_mc_ctx;

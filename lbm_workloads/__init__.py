@@ -55,6 +55,7 @@ class Workload:
     n0: Optional[float] = None
     forcing: str = "standard"    # "standard"; "diff": plus the diffusion-driven term;
                                  # "full": the whole corrected forcing
+    wall_velocity: Optional[List[List[float]]] = None   # [low, high] wall velocities
 
     @property
     def n_species(self):

@@ -23,6 +23,7 @@ class Params(ctypes.Structure):
         ("n_species", c_int32), ("bc", c_int32 * 3),
         ("molar_mass", c_double * 4), ("diff", (c_double * 4) * 4), ("tau1", c_double),
         ("g", c_double * 3), ("n0", c_double), ("forcing", c_int32), ("reserved", c_int32),
+        ("wall_velocity", (c_double * 3) * 2),
     ]
 
 

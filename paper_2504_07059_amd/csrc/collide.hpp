@@ -349,6 +349,70 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
     return isfinite(sgt) && isfinite(P0);
 }
 
+// Moving walls (the closing remark of Appendix A).  At a node next to a wall
+// moving along itself with velocity u_w, every direction a pointing away from
+// the wall gains the paper's term written for the reflected direction,
+//   2 w_a rho_i w_i (e_a.u_w)/c_s^2 = 6 w_a rho_i w_i (c_a.u_w)/c,
+// with rho_i and the mass fraction w_i of the streamed populations at the
+// node (the term adds no mass, so they do not depend on it).  Over the
+// reflected directions sum_a w_a c_a c_a = I/18 in the tangential components
+// (D2Q9 and D3Q19 alike), so the term raises u_i^eq = c sum_a c_a f_a/rho_i +
+// g/2 by w_i u_w/3.
+struct WallMove {
+    int axis, sigma;   // wall axis; -1 for the low wall, +1 for the high one
+    float u[3];
+};
+
+// Whether node (x, y, z) lies next to a moving wall; fills W if so.
+__device__ __forceinline__ bool moving_wall_at(const LatParams& P, int x, int y, int z,
+                                               WallMove& W) {
+    const int axis = P.wall_axis;
+    if (!P.moving || axis < 0) return false;
+    const int c = axis == 0 ? x : (axis == 1 ? y : z);
+    const int n = axis == 0 ? P.nx : (axis == 1 ? P.ny : P.nz);
+    int k;
+    if (c == 0) k = 0;
+    else if (c == n - 1) k = 1;
+    else return false;
+    W.axis = axis;
+    W.sigma = k == 0 ? -1 : 1;
+    W.u[0] = P.uw[k][0];
+    W.u[1] = P.uw[k][1];
+    W.u[2] = P.uw[k][2];
+    return W.u[0] != 0.0f || W.u[1] != 0.0f || W.u[2] != 0.0f;
+}
+
+// u_i^eq of every species after the moving-wall terms (rho: streamed densities)
+template <int NS>
+__device__ __forceinline__ void wall_shift_ue(const WallMove& W, const float (&rho)[NS],
+                                              float (&ue)[NS][3]) {
+    float R = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) R += rho[j];
+    const float iR3 = rcp_nr(R) * (1.0f / 3.0f);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const float wj = rho[j] * iR3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ue[j][d] = fmaf(wj, W.u[d], ue[j][d]);
+    }
+}
+
+// the moving-wall terms on the streamed deviations of one species (speed c,
+// streamed density rho_i, mass fraction w_i); mirror directions get exactly
+// opposite terms
+template <int LAT>
+__device__ __forceinline__ void wall_add_terms(const WallMove& W, float rho_i, float w_i, float c,
+                                               float (&F)[Lat<LAT>::Q]) {
+    using L = Lat<LAT>;
+    const float k = 6.0f * rho_i * w_i * rcp_nr(c);
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a) {
+        const int ca = W.axis == 0 ? L::cx(a) : (W.axis == 1 ? L::cy(a) : L::cz(a));
+        if (W.sigma * ca < 0) F[a] = fmaf(L::w(a) * k, cdot<LAT>(a, W.u[0], W.u[1], W.u[2]), F[a]);
+    }
+}
+
 // Collision of one node, all species, under the specific force g (the
 // constant one or the node's value of a force field).  On return P0[s] holds
 // the new stored rest population and F[s][a] (a >= 1) the stored deviations
@@ -356,10 +420,19 @@ __device__ __forceinline__ bool collide_species(const SpeciesConst& K, const flo
 template <int LAT, int NS, int FRC>
 __device__ __forceinline__ bool collide(float (&P0)[NS], float (&F)[NS][Lat<LAT>::Q],
                                         const CollConst& C, const float (&g)[3],
-                                        const float (&gi)[NS][3]) {
+                                        const float (&gi)[NS][3], bool mw, const WallMove& W) {
     float rho[NS], dlt[NS], ue[NS][3];
 #pragma unroll
     for (int s = 0; s < NS; ++s) species_moments<LAT>(P0[s], F[s], C.c[s], g, rho[s], dlt[s], ue[s]);
+    if (mw) {
+        wall_shift_ue<NS>(W, rho, ue);
+        float R = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) R += rho[s];
+        const float iR = rcp_nr(R);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) wall_add_terms<LAT>(W, rho[s], rho[s] * iR, C.c[s], F[s]);
+    }
     const Mix M = mixture<NS>(rho, ue, C);
     float y[NS][NS];
     tau_solve<NS>(rho, M.R, M.n, C, y);

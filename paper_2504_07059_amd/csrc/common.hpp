@@ -19,6 +19,8 @@ struct LatParams {
     int32_t n_species;
     int32_t tile_begin, tile_end;  // this lattice's range in the tile list
     int32_t forcing;               // 0: standard forcing term; 1: plus S_diff; 2: full
+    int32_t moving;                // a wall of the wall axis moves (uw nonzero)
+    float uw[2][3];                // velocities of the low / high wall (tangential)
     float lam[MAXS][3];            // (lambda_-1, lambda_0, lambda_+1) at Courant +c_s;
                                    // the three floats sum to exactly 1
     float c[MAXS];                 // c_s = sqrt(M_1/M_s)
@@ -61,6 +63,7 @@ struct Launch {
                          // node fields [lattice][N][nodes] (written by the pre-pass)
     const float* accel;  // force field k(x), dense node fields [lattice][d][nodes], or null
                          // (the constant g of each lattice)
+    int32_t moving;      // some lattice has a moving wall
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };

@@ -122,6 +122,26 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         if (q.forcing != p[0].forcing)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: every lattice needs the same forcing", l);
         if (q.reserved != 0) return fail(LBM_MC_ERR_INVALID, "lattice %d: reserved must be 0", l);
+        {
+            int wax = -1;
+            for (int a = 0; a < 3; ++a)
+                if (q.bc[a] == LBM_MC_WALL) wax = a;
+            for (int k = 0; k < 2; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    const double v = q.wall_velocity[k][a];
+                    if (!std::isfinite(v))
+                        return fail(LBM_MC_ERR_INVALID, "lattice %d: wall velocity not finite", l);
+                    if (v == 0.0) continue;
+                    if (wax < 0)
+                        return fail(LBM_MC_ERR_INVALID,
+                                    "lattice %d: a wall velocity needs a wall axis", l);
+                    if (a == wax)
+                        return fail(LBM_MC_ERR_INVALID,
+                                    "lattice %d: wall velocities must be tangential", l);
+                    if (q.lattice == LBM_MC_D2Q9 && a == 2)
+                        return fail(LBM_MC_ERR_INVALID, "lattice %d: no z velocity in 2-D", l);
+                }
+        }
     }
     return LBM_MC_OK;
 }
@@ -532,6 +552,8 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.forcing = c->params[0].forcing;
     L.dens = c->dens;
     L.accel = c->accel;
+    L.moving = 0;
+    for (const auto& h : c->hlp) L.moving |= h.moving;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -629,6 +651,8 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: only forcing = 0 is differentiated");
     if (c->accel)
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: a force-field context is not differentiated");
+    if (c->hlp[0].moving)
+        return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: moving walls are not differentiated");
     const size_t bytes = (size_t)c->layout.total * sizeof(float);
     if (!c->dmu) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
@@ -728,6 +752,13 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
         if ((uintptr_t)accel % 4)
             return fail(LBM_MC_ERR_INVALID, "the force field must be 4-byte aligned");
         for (int l = 0; l < n_lattices; ++l)
+            for (int k = 0; k < 2; ++k)
+                for (int a = 0; a < 3; ++a)
+                    if (p[l].wall_velocity[k][a] != 0.0)
+                        return fail(LBM_MC_ERR_UNSUPPORTED,
+                                    "lattice %d: a force field with moving walls is not provided",
+                                    l);
+        for (int l = 0; l < n_lattices; ++l)
             if (p[l].g[0] != 0.0 || p[l].g[1] != 0.0 || p[l].g[2] != 0.0)
                 return fail(LBM_MC_ERR_INVALID,
                             "lattice %d: g must be 0 when a force field is given", l);
@@ -788,6 +819,12 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
             if (q.bc[a] == LBM_MC_WALL) P.wall_axis = a;
         P.n_species = q.n_species;
         P.forcing = q.forcing;
+        P.moving = 0;
+        for (int k = 0; k < 2; ++k)
+            for (int a = 0; a < 3; ++a) {
+                P.uw[k][a] = (float)q.wall_velocity[k][a];
+                if (q.wall_velocity[k][a] != 0.0) P.moving = 1;
+            }
         for (int i = 0; i < MAXS; ++i) {
             if (i < nm.N) {
                 exact_triple(nm.c[i], P.lam[i]);

@@ -63,7 +63,7 @@ __device__ __forceinline__ void species_grads(const float* dens, const LatParams
     }
 }
 
-template <int LAT, int NS, int FRC, bool KF>
+template <int LAT, int NS, int FRC, int EXT>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -72,14 +72,17 @@ struct StepOp {
     const float* dens;      // FRC 2: this lattice's density fields
     const LatParams* P;
     int x, y;
-    const float* accel;     // KF: the force field
+    const float* accel;     // EXT 1: the force field
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned own) {
         float gi[NS][3] = {};
         if constexpr (FRC == 2) species_grads<LAT, NS>(dens, *P, x, y, m, gi);
         float g[3];
-        node_accel<LAT, KF>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
-        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi)) bad = true;
+        node_accel<LAT, EXT == 1>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
+        constexpr int DIM = Lat<LAT>::DIM;
+        WallMove W{};
+        const bool mw = EXT == 2 && moving_wall_at(*P, x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, W);
+        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi, mw, W)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             stb(D, s * Q, own, P0[s]);
@@ -89,7 +92,7 @@ struct StepOp {
     }
 };
 
-template <int LAT, int NS, int FRC, bool KF>
+template <int LAT, int NS, int FRC, int EXT>
 __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
                                               const LatParams* __restrict__ lps,
                                               const Tile* __restrict__ tiles, int ntiles,
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS, FRC, KF> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
+        StepOp<LAT, NS, FRC, EXT> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
                                     FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y,
                                     accel};
         march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, so several times more waves fit on a SIMD.
-template <int LAT, int NS, int FRC, bool KF>
+template <int LAT, int NS, int FRC, int EXT>
 struct SplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -138,11 +141,11 @@ struct SplitOp {
     const float* dens;       // FRC 2: this species' density field
     const LatParams* P;
     int x, y;
-    const float* accel;      // KF: the force field
+    const float* accel;      // EXT 1: the force field
     __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int m, unsigned own) {
         constexpr int DIM = Lat<LAT>::DIM;
         float g[3];
-        node_accel<LAT, KF>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
+        node_accel<LAT, EXT == 1>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
         float rho_s, dlt_s, ue_s[3];
         species_moments<LAT>(P0, F, K.c, g, rho_s, dlt_s, ue_s);
         float4 (*X)[64] = xch[m & 1];
@@ -173,6 +176,21 @@ struct SplitOp {
             ue[j][1] = v.z;
             ue[j][2] = v.w;
         }
+        WallMove W{};
+        if (EXT == 2 && moving_wall_at(*P, x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, W)) {
+            wall_shift_ue<NS>(W, rho, ue);
+            float R = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) R += rho[j];
+            wall_add_terms<LAT>(W, rho_s, rho_s * rcp_nr(R), K.c, F);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                if (i != s) continue;
+                ue_s[0] = ue[i][0];
+                ue_s[1] = ue[i][1];
+                ue_s[2] = ue[i][2];
+            }
+        }
         const Mix M = mixture<NS>(rho, ue, C);
         float y[NS][NS];
         tau_solve<NS>(rho, M.R, M.n, C, y);
@@ -194,7 +212,7 @@ struct SplitOp {
     }
 };
 
-template <int LAT, int NS, int FRC, bool KF>
+template <int LAT, int NS, int FRC, int EXT>
 __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
                                                     float* __restrict__ dst,
                                                     const LatParams* __restrict__ lps,
@@ -224,7 +242,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         // the species' own constants, read with the uniform species index
         // (scalar loads; no run-time indexing of register arrays)
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-        SplitOp<LAT, NS, FRC, KF> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+        SplitOp<LAT, NS, FRC, EXT> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
                                               P.kdiff[s], P.cs2[s]},
                                  xch, reinterpret_cast<float4 (*)[NS][64]>(xgr), s, lane,
@@ -338,7 +356,7 @@ __global__ void __launch_bounds__(256) k_density_split(const float* __restrict__
 // velocity), rho_i = x_i M_i n0, evaluated in double and stored as
 // P0 = f_0 and g_a = f_a - (w_a/w_0) P0 + w_a (f_0 - P0)/(1 - w_0) in f0_out;
 // then one collision, stored in ft_out.
-template <int LAT, int NS, int FRC, bool KF>
+template <int LAT, int NS, int FRC, int EXT>
 __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps, int lat,
                                               const double* __restrict__ x0,
                                               const float* __restrict__ accel,
@@ -360,7 +378,7 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
         const int z = (int)(r / P.ny);
         const int64_t own = P.base + ((int64_t)z * P.ny + y) * P.pitch + x;
         float g[3];
-        node_accel<LAT, KF>(accel, P, C.g, id, g);
+        node_accel<LAT, EXT == 1>(accel, P, C.g, id, g);
         float P0[NS], F[NS][Q];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -395,7 +413,8 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
                                           P.ny, P.nz, P.wall_axis, x, y, z, gi[s]);
             }
         }
-        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi)) bad = true;
+        if (!collide<LAT, NS, FRC>(P0, F, C, g, gi, false, WallMove{}))   // f(0): not streamed
+            bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             ft_out[(int64_t)(s * Q) * P.plane + own] = P0[s];
@@ -418,6 +437,8 @@ struct MomOp {
     int nx, ny, x, y;
     CollConst C;
     const float* accel;      // this lattice's force field, or null (constant g)
+    const LatParams* P;
+    bool streamed;           // the populations come from a stream (not f(0))
     double acc[NS + 3];
     __device__ __forceinline__ void operator()(float (&P0)[NS], float (&F)[NS][Q], int m,
                                                unsigned) {
@@ -432,6 +453,9 @@ struct MomOp {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             species_moments<LAT>(P0[s], F[s], C.c[s], g, rho[s], dlt[s], ue[s]);
+        WallMove W;
+        if (streamed && moving_wall_at(*P, x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, W))
+            wall_shift_ue<NS>(W, rho, ue);
         float R = 0.0f, n = 0.0f, U[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -479,6 +503,8 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
     op.nx = P.nx; op.ny = P.ny; op.x = x; op.y = y;
     op.C = coll_const(P);
     op.accel = accel ? accel + P.field_base * DIM : nullptr;
+    op.P = &P;
+    op.streamed = !direct;
 #pragma unroll
     for (int q = 0; q < NS + 3; ++q) op.acc[q] = 0.0;
     if (x < P.nx && (DIM == 2 || y < P.ny)) {
@@ -543,19 +569,22 @@ __global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lp
 }
 
 // ---------------------------------------------------------------- launchers
-// Calls fn(lattice, species count, forcing, force field) with the four as
-// compile-time constants.
+// Calls fn(lattice, species count, forcing, extension) with the four as
+// compile-time constants; extension 0: constant g and resting walls, 1: a
+// force field, 2: moving walls.
 template <typename Fn>
-static hipError_t by_shape(int lattice, int ns, int frc, bool kf, Fn&& fn) {
+static hipError_t by_shape(int lattice, int ns, int frc, int ext, Fn&& fn) {
     using std::integral_constant;
-    auto with_kf = [&](auto lat, auto n, auto f) -> hipError_t {
-        if (kf) return fn(lat, n, f, integral_constant<bool, true>{});
-        return fn(lat, n, f, integral_constant<bool, false>{});
+    auto with_ext = [&](auto lat, auto n, auto f) -> hipError_t {
+        if (ext == 0) return fn(lat, n, f, integral_constant<int, 0>{});
+        if (ext == 1) return fn(lat, n, f, integral_constant<int, 1>{});
+        if (ext == 2) return fn(lat, n, f, integral_constant<int, 2>{});
+        return hipErrorInvalidValue;
     };
     auto with_frc = [&](auto lat, auto n) -> hipError_t {
-        if (frc == 0) return with_kf(lat, n, integral_constant<int, 0>{});
-        if (frc == 1) return with_kf(lat, n, integral_constant<int, 1>{});
-        if (frc == 2) return with_kf(lat, n, integral_constant<int, 2>{});
+        if (frc == 0) return with_ext(lat, n, integral_constant<int, 0>{});
+        if (frc == 1) return with_ext(lat, n, integral_constant<int, 1>{});
+        if (frc == 2) return with_ext(lat, n, integral_constant<int, 2>{});
         return hipErrorInvalidValue;
     };
     auto with_ns = [&](auto lat) -> hipError_t {
@@ -571,11 +600,10 @@ static hipError_t by_shape(int lattice, int ns, int frc, bool kf, Fn&& fn) {
 
 hipError_t launch_step(int lattice, int ns, const Launch& L) {
     if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
-    return by_shape(lattice, ns, L.forcing, L.accel != nullptr,
-                    [&](auto lat, auto n, auto frc, auto kf) {
+    return by_shape(lattice, ns, L.forcing, L.accel ? 1 : (L.moving ? 2 : 0),
+                    [&](auto lat, auto n, auto frc, auto ex) {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
-                      FRC = decltype(frc)::value;
-        constexpr bool KF = decltype(kf)::value;
+                      FRC = decltype(frc)::value, EXT = decltype(ex)::value;
         if (FRC == 2) {
             if (!L.dens) return hipErrorInvalidValue;
             // (the force does not enter the densities)
@@ -589,11 +617,11 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
             if (e != hipSuccess) return e;
         }
         if (L.split)
-            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, KF>), dim3(L.grid), dim3(64, NS), 0,
+            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(64, NS), 0,
                                L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
                                L.accel, L.flag);
         else
-            hipLaunchKernelGGL((k_step<LAT, NS, FRC, KF>), dim3(L.grid), dim3(L.bx, L.by), 0,
+            hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(L.bx, L.by), 0,
                                L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.accel,
                                L.flag);
         return hipGetLastError();
@@ -605,12 +633,12 @@ hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const 
                        unsigned* flag, hipStream_t s) {
     const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
     const int64_t blocks = std::min<int64_t>((nodes + 255) / 256, 65536);
-    return by_shape(lattice, ns, h.forcing, accel != nullptr,
-                    [&](auto la, auto n, auto frc, auto kf) {
+    // the initial collision acts on f(0), which has not been streamed: no wall terms
+    return by_shape(lattice, ns, h.forcing, accel ? 1 : 0,
+                    [&](auto la, auto n, auto frc, auto ex) {
         constexpr int LAT = decltype(la)::value, NS = decltype(n)::value,
-                      FRC = decltype(frc)::value;
-        constexpr bool KF = decltype(kf)::value;
-        hipLaunchKernelGGL((k_init<LAT, NS, FRC, KF>), dim3((unsigned)blocks), dim3(256), 0, s,
+                      FRC = decltype(frc)::value, EXT = decltype(ex)::value;
+        hipLaunchKernelGGL((k_init<LAT, NS, FRC, EXT>), dim3((unsigned)blocks), dim3(256), 0, s,
                            lp, lat, x0, accel, f0, ft, flag);
         return hipGetLastError();
     });

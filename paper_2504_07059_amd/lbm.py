@@ -15,10 +15,12 @@ LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
 
 
 def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
-                walls=(False, False, False), n0=0.0, forcing=0):
+                walls=(False, False, False), n0=0.0, forcing=0, wall_velocity=None):
     """Fill one lbm_mc_params struct (forcing: 0 or "standard" for the
     standard forcing term, 1 or "diff" to add the diffusion-driven term, 2 or
-    "full" for the whole corrected forcing, - S_p + S_rho + S_diff)."""
+    "full" for the whole corrected forcing, - S_p + S_rho + S_diff;
+    wall_velocity: optional [[low], [high]] tangential velocities of the two
+    walls of the wall axis)."""
     p = Params()
     p.lattice = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}[lattice] if isinstance(lattice, str) \
         else int(lattice)
@@ -38,12 +40,15 @@ def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
     p.forcing = {"standard": 0, "diff": 1, "full": 2}[forcing] if isinstance(forcing, str) \
         else int(forcing)
     p.reserved = 0
+    for k in range(2):
+        for a in range(3):
+            p.wall_velocity[k][a] = float(wall_velocity[k][a]) if wall_velocity is not None else 0.0
     return p
 
 
 def params_from_workload(w):
     return make_params(w.lattice, w.nx, w.ny, w.nz, w.masses, w.diff, w.tau1, w.g,
-                       w.walls, w.n0 or 0.0, w.forcing)
+                       w.walls, w.n0 or 0.0, w.forcing, w.wall_velocity)
 
 
 def _arr(params):

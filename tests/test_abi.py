@@ -40,10 +40,11 @@ def test_params_struct_layout_matches_c():
 #include <stddef.h>
 #include "lbm_mc.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbm_mc_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbm_mc_params),
          offsetof(lbm_mc_params, molar_mass), offsetof(lbm_mc_params, diff),
          offsetof(lbm_mc_params, tau1), offsetof(lbm_mc_params, g),
-         offsetof(lbm_mc_params, n0), offsetof(lbm_mc_params, forcing));
+         offsetof(lbm_mc_params, n0), offsetof(lbm_mc_params, forcing),
+         offsetof(lbm_mc_params, wall_velocity));
   return 0;
 }
 """
@@ -56,7 +57,7 @@ int main(void) {
                                                check=True).stdout.split()]
     P = L.Params
     assert vals == [ctypes.sizeof(P), P.molar_mass.offset, P.diff.offset, P.tau1.offset,
-                    P.g.offset, P.n0.offset, P.forcing.offset]
+                    P.g.offset, P.n0.offset, P.forcing.offset, P.wall_velocity.offset]
 
 
 def _tube(nx=64, ny=4, N=3, **kw):
@@ -208,3 +209,31 @@ def test_init_field_rejects_bad_arguments_before_touching_the_gpu():
                                  ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
                                  ctypes.byref(ctx))
     assert st == 1 and b"g must be 0" in L.lib.lbm_mc_last_error()
+
+
+def test_check_wall_velocities():
+    """Wall velocities must be finite, tangential, on a lattice with a wall
+    axis, with no z component in 2-D; a force field with moving walls is
+    rejected before any device work."""
+    from paper_2504_07059_amd.lbm import check_problem
+    p = _tube(wall_velocity=[[0, 0.01, 0], [0, -0.02, 0]])
+    assert check_problem(p, _x0(p))[0] == 0
+    for uw, frag in (([[0.01, 0, 0], [0, 0, 0]], "tangential"),
+                     ([[0, 0, 0.01], [0, 0, 0]], "z velocity"),
+                     ([[0, float("nan"), 0], [0, 0, 0]], "finite")):
+        p = _tube(wall_velocity=uw)
+        st, _, msg = check_problem(p, _x0(p))
+        assert st == 1 and frag in msg, (uw, msg)
+    p = _tube(walls=(False, False, False), wall_velocity=[[0, 0.01, 0], [0, 0, 0]])
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 1 and "wall axis" in msg
+    L = _lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    ctx = ctypes.c_void_p()
+    p = _tube(g=(0.0, 0.0, 0.0), wall_velocity=[[0, 0.01, 0], [0, 0, 0]])
+    x = np.ascontiguousarray(_x0(p))
+    arr = (L.Params * 1)(p)
+    st = L.lib.lbm_mc_init_field(arr, 1, x.ctypes.data_as(dp), ctypes.c_void_p(1 << 20),
+                                 ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
+                                 ctypes.byref(ctx))
+    assert st == 2 and b"moving walls" in L.lib.lbm_mc_last_error()
