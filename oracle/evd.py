@@ -529,6 +529,54 @@ def moving_wall_terms(model, f):
     return out
 
 
+def stream_equilibrium_walls(model, ft):
+    """The comparison boundary of Sec. 4.1 (the equilibrium scheme set against
+    the proposed wall scheme for the Ga = 0 Loschmidt tube): the solid nodes
+    beyond a wall hold f = f^(0)(rho_s, u = 0) = w_alpha rho_s, with rho_s the
+    density of the adjacent fluid node (the wall-layer node at the same
+    tangential position), and the fluid streams from them with the same
+    interpolation as from any node; no Appendix A terms.  A negative control:
+    the paper shows that it does not conserve mass."""
+    N, Q = model.N, model.lat.Q
+    e = model.velocities()
+    dim = model.lat.dim
+    rho = ft.sum(dim=1)                                     # [N, nz, ny, nx]
+    w = model.lat.w
+    offs = [(kx, ky, kz) for kz in ((-1, 0, 1) if dim == 3 else (0,))
+            for ky in (-1, 0, 1) for kx in (-1, 0, 1)]
+    lam = [[[lagrange_weights(float(e[i, al, a])) for a in range(3)]
+            for al in range(Q)] for i in range(N)]
+    out = torch.zeros_like(ft)
+    for k in offs:
+        wk = torch.tensor([[lam[i][al][0][k[0] + 1] * lam[i][al][1][k[1] + 1]
+                            * lam[i][al][2][k[2] + 1] for al in range(Q)]
+                           for i in range(N)], dtype=DTYPE)
+        if not bool((wk != 0).any()):
+            continue
+        fluid = _shift_source(model, ft, k)                 # 0 at solid sources
+        # rho_s of the adjacent fluid node: clamp the source into the lattice
+        # along the wall axis, shift as usual along the others
+        rs = rho
+        solid = torch.zeros(rho.shape[1:], dtype=torch.bool)
+        for a in range(3):
+            if k[a] == 0:
+                continue
+            d = AXIS_DIM[a]
+            n = model.shape_axis(a)
+            if model.walls[a]:
+                idx = torch.clamp(torch.arange(n) + k[a], 0, n - 1)
+                rs = rs.index_select(d, idx)
+                bad = (torch.arange(n) + k[a] < 0) | (torch.arange(n) + k[a] >= n)
+                shape = [1, 1, 1]
+                shape[d] = n
+                solid = solid | bad.reshape(shape)
+            else:
+                rs = torch.roll(rs, shifts=-k[a], dims=d)
+        eq = w[None, :, None, None, None] * rs[:, None] * solid.to(DTYPE)[None, None]
+        out = out + wk[:, :, None, None, None] * (fluid + eq)
+    return out
+
+
 def step(model, f):
     """One time step: f(t) -> f(t+1) = stream(collide(f(t)))."""
     return stream(model, collide(model, f))
