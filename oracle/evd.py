@@ -38,6 +38,11 @@ Readings taken where the paper is silent (each repeated at its function):
      differences along each lattice axis (periodic axes wrap); at a node next
      to a wall the second-order one-sided difference into the fluid is used
      (a wall axis then needs at least 3 nodes);
+  R11 where walls on several axes meet (edges, corners; Appendix A treats
+     single walls), the wall rule is read as the return, to the wall node,
+     of what its populations would stream beyond the walls, split by the set
+     of walls crossed (see _wall_returns); it reduces to Appendix A for one
+     wall, to halfway bounce-back at c = 1, and conserves mass;
   R10 the moving-wall term of Appendix A takes rho_i and the mass fraction
      w_i of the streamed populations at the wall node (the term adds no mass,
      so they do not depend on it), and a wall moves only along itself.
@@ -101,8 +106,7 @@ class Model:
         self.g = torch.as_tensor(self.g, dtype=DTYPE)
         if self.lat.dim == 2 and self.nz != 1:
             raise ValueError("2-D lattice needs nz = 1")
-        if sum(bool(w) for w in self.walls) > 1:
-            raise ValueError("walls on more than one axis are not supported")
+
         for a, w in enumerate(self.walls):
             if w and self.shape_axis(a) < 2:
                 raise ValueError("a wall axis needs at least 2 nodes")
@@ -113,6 +117,8 @@ class Model:
             ax = [a for a in range(3) if self.walls[a]]
             if not ax:
                 raise ValueError("a wall velocity needs a wall axis")
+            if len(ax) > 1:
+                raise ValueError("moving walls need a single wall axis")
             if bool((self.wall_velocity[:, ax[0]] != 0).any()):
                 raise ValueError("wall velocities must be tangential to the wall")
             if self.lat.dim == 2 and bool((self.wall_velocity[:, 2] != 0).any()):
@@ -429,6 +435,67 @@ def _shift_source(model, plane, k):
     return out
 
 
+def _wall_returns(model, ft, lam, walled):
+    """The impermeable-wall terms of Appendix A (readings R2, R11), read as
+    the return of what a wall-layer population would stream beyond the walls:
+    source f~_beta(O) at a node O next to walls sends weight Lambda_k(e_beta)
+    to the target O - k; for each set R of walls that such targets lie beyond,
+    the lost weight
+        prod_{a in R} lambda_{-s_a}(e_beta,a) prod_{a next to O, not in R}
+        (1 - lambda_{-s_a}(e_beta,a))
+    (s_a = -1 at the low wall of axis a, +1 at the high one) is returned to O,
+    into the reversed direction if beta moves toward a wall of R, else into
+    beta itself.  With one wall this is term by term the Appendix A rule
+    (lambda_{-s}(e_alpha) f~_alpha(O) + lambda_{-s}(e_alphabar) f~_alphabar(O)
+    for alpha pointing away from the wall); at c = 1 it is halfway
+    bounce-back, also into corners; every source keeps its whole weight, so
+    species mass is conserved."""
+    N, Q = model.N, model.lat.Q
+    dirs, opp = model.lat.dirs, model.lat.opp
+    add = torch.zeros_like(ft)
+    choices = []
+    for a in walled:
+        n = model.shape_axis(a)
+        choices.append([(-1, 0), (1, n - 1)] + ([(0, None)] if n > 2 else []))
+    import itertools
+    for pat in itertools.product(*choices):
+        adj = [(a, s) for a, (s, _) in zip(walled, pat) if s != 0]
+        if not adj:
+            continue
+        # nodes of this adjacency pattern
+        mask = torch.ones(model.nz, model.ny, model.nx, dtype=torch.bool)
+        for a, (s, idx) in zip(walled, pat):
+            d = AXIS_DIM[a] + 4                               # spatial dim in [nz, ny, nx]
+            n = model.shape_axis(a)
+            sel = torch.zeros(n, dtype=torch.bool)
+            if s == 0:
+                sel[1:n - 1] = True
+            else:
+                sel[idx] = True
+            shape = [1, 1, 1]
+            shape[d - 1] = n
+            mask = mask & sel.reshape(shape)
+        C = torch.zeros(N, Q, Q, dtype=DTYPE)                # [species, dest, source]
+        for r in range(1, len(adj) + 1):
+            for R in itertools.combinations(range(len(adj)), r):
+                for i in range(N):
+                    for b in range(Q):
+                        lost = 1.0
+                        toward = False
+                        for t, (a, s) in enumerate(adj):
+                            lm = lam[i][b][a][-s + 1]
+                            if t in R:
+                                lost *= lm
+                                toward = toward or s * dirs[b][a] > 0
+                            else:
+                                lost *= 1.0 - lm
+                        if lost != 0.0:
+                            C[i, opp[b] if toward else b, b] += lost
+        ret = torch.einsum("ndb,nbzyx->ndzyx", C, ft)
+        add = add + torch.where(mask[None, None], ret, torch.zeros_like(ret))
+    return add
+
+
 def stream(model, ft):
     """Pull streaming with the second-order interpolation of eq.
     (Second_order_spatial_interpolation) (reading R1), generalised to
@@ -463,29 +530,10 @@ def stream(model, ft):
         if not bool((wk != 0).any()):
             continue
         out = out + wk[:, :, None, None, None] * _shift_source(model, ft, k)
-    # Appendix A wall terms.
-    for a in range(3):
-        if not model.walls[a]:
-            continue
-        n = model.shape_axis(a)
-        d = AXIS_DIM[a]
-        for sigma in (-1, +1):
-            layer = 0 if sigma < 0 else n - 1
-            wa = torch.zeros(N, Q, dtype=DTYPE)
-            wb = torch.zeros(N, Q, dtype=DTYPE)
-            for i in range(N):
-                for al in range(Q):
-                    if sigma * model.lat.dirs[al][a] >= 0:
-                        continue
-                    ab = model.lat.opp[al]
-                    wa[i, al] = lam[i][al][a][-sigma + 1]
-                    wb[i, al] = lam[i][ab][a][-sigma + 1]
-            here = ft.select(d, layer)                       # [N, Q, ., .]
-            opp = here[:, model.lat.opp]
-            add = wa[:, :, None, None] * here + wb[:, :, None, None] * opp
-            idx = [slice(None)] * 5
-            idx[d] = layer
-            out[tuple(idx)] = out[tuple(idx)] + add
+    # Appendix A wall terms (reading R2; reading R11 where walls meet).
+    walled = [a for a in range(3) if model.walls[a]]
+    if walled:
+        out = out + _wall_returns(model, ft, lam, walled)
     if model.wall_velocity is not None:
         out = moving_wall_terms(model, out)
     return out
