@@ -57,7 +57,8 @@ extern "C" {
 typedef enum lbm_mc_status {
     LBM_MC_OK = 0,
     LBM_MC_ERR_INVALID = 1,     /* an argument is invalid (message says which) */
-    LBM_MC_ERR_UNSUPPORTED = 2, /* valid in principle, not provided (walls on two axes, N > 4) */
+    LBM_MC_ERR_UNSUPPORTED = 2, /* valid in principle, not provided (N > 4, moving walls on
+                                   several axes, ...; the message says which) */
     LBM_MC_ERR_HIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
     LBM_MC_ERR_UNSTABLE = 4,    /* linear stability pre-check of the cross relaxation failed */
     LBM_MC_ERR_NONFINITE = 5    /* a step produced a non-finite population */
@@ -74,7 +75,12 @@ typedef struct lbm_mc_params {
     int32_t n_species;      /* 2..4 */
     int32_t bc[3];          /* per axis x, y, z: LBM_MC_PERIODIC, or LBM_MC_WALL =
                                impermeable halfway walls beyond both ends of the axis
-                               (Appendix A).  At most one axis may have walls. */
+                               (Appendix A).  Walls may close several axes (a channel
+                               edge or a box corner): a population of a wall node that
+                               would cross several walls returns to the node, in the
+                               reversed direction if it moves toward any crossed wall,
+                               else in its own (mass conserved; reading of Appendix A
+                               for corners). */
     double molar_mass[4];   /* molar masses, non-decreasing; any unit (normalised) */
     double diff[4][4];      /* pair diffusivities D_ij in lattice units, symmetric,
                                > 0 off the diagonal; the diagonal is ignored */
@@ -96,7 +102,9 @@ typedef struct lbm_mc_params {
     int32_t reserved;       /* must be 0 */
     double wall_velocity[2][3]; /* velocity of the wall at the low ([0]) and high ([1]) end
                                of the wall axis, tangential to it (the component along
-                               the wall axis must be 0; all 0 without walls).  A moving
+                               the wall axis must be 0; all 0 without walls; moving
+                               walls need walls on exactly one axis, else
+                               LBM_MC_ERR_UNSUPPORTED).  A moving
                                wall adds the term of Appendix A's closing remark,
                                -2 omega_a rho_i w_i (e_a.u_w)/c_{s,i}^2 for the reflected
                                direction, with rho_i and the mass fraction w_i of the
@@ -243,7 +251,8 @@ lbm_mc_status lbm_mc_restore(lbm_mc_ctx* ctx, const float* cur, const float* pre
  * grad += (dPhi/dtheta)^T lam_in.  lam_out must not alias lam_in or f_prev.
  * Uses a context-owned scratch buffer of one population buffer (allocated on
  * first use).  Errors: LBM_MC_ERR_INVALID, LBM_MC_ERR_UNSUPPORTED (batched
- * context), LBM_MC_ERR_HIP.
+ * context, forcing other than 0, a force field, moving walls, walls on
+ * several axes), LBM_MC_ERR_HIP.
  */
 lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* ctx, const float* f_prev, const float* lam_in,
                                   float* lam_out, double* grad);

@@ -231,8 +231,9 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
     const Buf M = make_buf(mu + P.base, lf, P.plane);
     const Buf O = make_buf(lamout + P.base, lf, P.plane);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-    const bool wx = G.wall_axis == 0, wy = DIM == 3 && G.wall_axis == 1,
-               wm = G.wall_axis == Fr::MA;
+    // (the reverse step is provided for at most one wall axis)
+    const bool wx = (G.walls & 1) != 0, wy = DIM == 3 && (G.walls & 2) != 0,
+               wm = (G.walls & (1 << Fr::MA)) != 0;
     const int xm = nbr(x, -1, G.nx, wx), xp = nbr(x, 1, G.nx, wx);
     int ym = 0, yp = 0;
     if (DIM == 3) {
@@ -255,8 +256,8 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
         const unsigned bmo[3] = {mmv < 0 ? kSolid : (unsigned)(mmv - m) * lsb, 0u,
                                  mpv < 0 ? kSolid : (unsigned)(mpv - m) * lsb};
         const int sm = wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
-        const int axis = G.wall_axis;
-        const int side = axis == 0 ? sx : (axis == Fr::MA ? sm : sy);
+        const int axis = wx ? 0 : (wm ? Fr::MA : 1);
+        const int side = wx ? sx : (wm ? sm : sy);
         float lf_[Q];
         lf_[0] = ldb(M, pb0, own);
         if (s == 0) {

@@ -224,16 +224,16 @@ __device__ __forceinline__ float axis_diff(At at, int i, int n, bool wall) {
 }
 
 // Gradient of a dense node field (node index (z ny + y) nx + x) at (x, y, z)
-// of a lattice with the given shape and wall axis (-1: none).
+// of a lattice with the given shape and wall mask (bit a: walls on axis a).
 template <int DIM, class Phi>
-__device__ __forceinline__ void field_grad(Phi phi, int nx, int ny, int nz, int wall_axis, int x,
+__device__ __forceinline__ void field_grad(Phi phi, int nx, int ny, int nz, int wall_mask, int x,
                                            int y, int z, float (&g)[3]) {
     g[0] = axis_diff([&](int j) { return phi(((int64_t)z * ny + y) * nx + j); }, x, nx,
-                     wall_axis == 0);
+                     (wall_mask & 1) != 0);
     g[1] = axis_diff([&](int j) { return phi(((int64_t)z * ny + j) * nx + x); }, y, ny,
-                     wall_axis == 1);
+                     (wall_mask & 2) != 0);
     g[2] = DIM == 3 ? axis_diff([&](int j) { return phi(((int64_t)j * ny + y) * nx + x); }, z, nz,
-                                wall_axis == 2)
+                                (wall_mask & 4) != 0)
                     : 0.0f;
 }
 
@@ -367,7 +367,7 @@ struct WallMove {
 __device__ __forceinline__ bool moving_wall_at(const LatParams& P, int x, int y, int z,
                                                WallMove& W) {
     const int axis = P.wall_axis;
-    if (!P.moving || axis < 0) return false;
+    if (!P.moving || axis < 0 || axis > 2) return false;
     const int c = axis == 0 ? x : (axis == 1 ? y : z);
     const int n = axis == 0 ? P.nx : (axis == 1 ? P.ny : P.nz);
     int k;

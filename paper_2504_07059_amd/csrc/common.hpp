@@ -15,7 +15,9 @@ struct LatParams {
     int64_t base;                  // float offset of this lattice in a population buffer
     int64_t plane;                 // floats per (species, direction) plane = nz*ny*pitch
     int64_t field_base;            // node offset of this lattice in dense node fields
-    int32_t wall_axis;             // -1: periodic everywhere; 0/1/2: walls at both ends
+    int32_t wall_axis;             // -1: periodic everywhere; 0/1/2: the one wall axis (walls
+                                   // at both ends); 3: walls on several axes
+    int32_t wall_mask;             // bit a set: walls at both ends of axis a
     int32_t n_species;
     int32_t tile_begin, tile_end;  // this lattice's range in the tile list
     int32_t forcing;               // 0: standard forcing term; 1: plus S_diff; 2: full

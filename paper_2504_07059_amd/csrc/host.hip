@@ -86,9 +86,7 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         }
         if (q.lattice == LBM_MC_D2Q9 && q.bc[2] == LBM_MC_WALL)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: no z walls in 2-D", l);
-        if (walls > 1)
-            return fail(LBM_MC_ERR_UNSUPPORTED,
-                        "lattice %d: walls on more than one axis (corners) are not supported", l);
+
         const int N = q.n_species;
         for (int i = 0; i < N; ++i) {
             if (!(q.molar_mass[i] > 0.0) || !std::isfinite(q.molar_mass[i]))
@@ -135,6 +133,9 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
                     if (wax < 0)
                         return fail(LBM_MC_ERR_INVALID,
                                     "lattice %d: a wall velocity needs a wall axis", l);
+                    if (walls > 1)
+                        return fail(LBM_MC_ERR_UNSUPPORTED,
+                                    "lattice %d: moving walls need a single wall axis", l);
                     if (a == wax)
                         return fail(LBM_MC_ERR_INVALID,
                                     "lattice %d: wall velocities must be tangential", l);
@@ -653,6 +654,8 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: a force-field context is not differentiated");
     if (c->hlp[0].moving)
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: moving walls are not differentiated");
+    if (c->hlp[0].wall_axis > 2)
+        return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: walls on several axes are not differentiated");
     const size_t bytes = (size_t)c->layout.total * sizeof(float);
     if (!c->dmu) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
@@ -815,8 +818,12 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
         P.plane = (int64_t)q.nz * q.ny * lo.pitch[l];
         P.field_base = lo.field[l];
         P.wall_axis = -1;
+        P.wall_mask = 0;
         for (int a = 0; a < 3; ++a)
-            if (q.bc[a] == LBM_MC_WALL) P.wall_axis = a;
+            if (q.bc[a] == LBM_MC_WALL) {
+                P.wall_axis = P.wall_mask ? 3 : a;
+                P.wall_mask |= 1 << a;
+            }
         P.n_species = q.n_species;
         P.forcing = q.forcing;
         P.moving = 0;

@@ -64,6 +64,16 @@ __device__ __forceinline__ Buf make_buf(const float* base, int64_t floats, int64
 // 0, which is exactly the contribution of a solid (beyond-the-wall) source.
 constexpr unsigned kSolid = 0x80000000u;
 
+// Sum of two byte offsets where either may carry kSolid.  Offsets are added as
+// signed 32-bit values with saturation: an in-lattice offset plus a
+// neighbour step stays exact, and a sum with kSolid in it stays at or below
+// INT_MIN plus a few steps, out of range as an unsigned offset.  A plain add
+// would let two markers (the node next to walls on two axes reading the
+// corner source beyond both) cancel modulo 2^32 into an in-range read.
+__device__ __forceinline__ unsigned oadd(unsigned a, unsigned b) {
+    return (unsigned)__builtin_elementwise_add_sat((int)a, (int)b);
+}
+
 // value of plane p at byte offset `vb` (per lane)
 __device__ __forceinline__ float ldb(const Buf& b, int p, unsigned vb) {
     return __builtin_bit_cast(
@@ -120,8 +130,8 @@ struct NbLoad {
     __device__ __forceinline__ void trip(const Buf& b, int p, unsigned row, const Col& c,
                                          float& m, float& z, float& q) const {
         z = ldb(b, p, row);
-        m = ldb(b, p, row + c.bxm);
-        q = ldb(b, p, row + c.bxp);
+        m = ldb(b, p, oadd(row, c.bxm));
+        q = ldb(b, p, oadd(row, c.bxp));
     }
 };
 
@@ -138,7 +148,7 @@ struct NbWave {
     __device__ __forceinline__ void trip(const Buf& b, int p, unsigned row, const Col&,
                                          float& m, float& z, float& q) const {
         z = ldb(b, p, row);
-        const float h = ldb(b, p, row + hx);
+        const float h = ldb(b, p, oadd(row, hx));
         m = from_left(h, z);
         q = from_right(h, z);
     }
@@ -170,8 +180,8 @@ __device__ __forceinline__ float hpass(const Buf& b, int p, unsigned cen, const 
     } else {
         const W3 wy = wsel(Q1, L);
         float v = wy.z * xpass<Q0>(b, p, cen, c, wx, nb);
-        v = fmaf(wy.m, xpass<Q0>(b, p, cen + c.bym, c, wx, nb), v);
-        v = fmaf(wy.p, xpass<Q0>(b, p, cen + c.byp, c, wx, nb), v);
+        v = fmaf(wy.m, xpass<Q0>(b, p, oadd(cen, c.bym), c, wx, nb), v);
+        v = fmaf(wy.p, xpass<Q0>(b, p, oadd(cen, c.byp), c, wx, nb), v);
         return v;
     }
 }
@@ -192,8 +202,8 @@ __device__ __forceinline__ RhoLayer rho_layer(const Buf& b, int p, unsigned cen,
     r.dxm = m - r.c;
     r.dxp = q - r.c;
     if constexpr (Lat<LAT>::DIM == 3) {
-        r.dym = ldb(b, p, cen + c.bym) - r.c;
-        r.dyp = ldb(b, p, cen + c.byp) - r.c;
+        r.dym = ldb(b, p, oadd(cen, c.bym)) - r.c;
+        r.dyp = ldb(b, p, oadd(cen, c.byp)) - r.c;
     } else {
         r.dym = r.dyp = 0.0f;
     }
@@ -202,7 +212,7 @@ __device__ __forceinline__ RhoLayer rho_layer(const Buf& b, int p, unsigned cen,
 
 // Per-lattice constants the gather needs, kept in scalar registers.
 struct GatherConst {
-    int nx, ny, nz, pitch, nm, wall_axis, lstride;   // lstride: floats per layer
+    int nx, ny, nz, pitch, nm, walls, lstride;   // walls: wall mask; lstride: floats per layer
     float lam[MAXS][3];
 };
 
@@ -210,7 +220,7 @@ __device__ __forceinline__ GatherConst gather_const(const LatParams& P, int dim)
     GatherConst g;
     g.nx = P.nx; g.ny = P.ny; g.nz = P.nz; g.pitch = P.pitch;
     g.nm = dim == 2 ? P.ny : P.nz;
-    g.wall_axis = P.wall_axis;
+    g.walls = P.wall_mask;
     g.lstride = dim == 2 ? P.pitch : P.ny * P.pitch;
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
@@ -245,9 +255,9 @@ template <int LAT>
 __device__ __forceinline__ ColGeom col_geom(const GatherConst& G, int x, int y) {
     constexpr int DIM = Lat<LAT>::DIM;
     ColGeom g;
-    g.wx = G.wall_axis == 0;
-    g.wy = DIM == 3 && G.wall_axis == 1;
-    g.wm = G.wall_axis == Frame<LAT>::MA;
+    g.wx = (G.walls & 1) != 0;
+    g.wy = DIM == 3 && (G.walls & 2) != 0;
+    g.wm = (G.walls & (1 << Frame<LAT>::MA)) != 0;
     const int xm = nbr(x, -1, G.nx, g.wx), xp = nbr(x, 1, G.nx, g.wx);
     g.col.sxm = xm < 0;
     g.col.sxp = xp < 0;
@@ -271,7 +281,7 @@ __device__ __forceinline__ ColGeom col_geom(const GatherConst& G, int x, int y) 
 
 // byte offset of the column in layer ml (kSolid beyond a wall)
 __device__ __forceinline__ unsigned layer_off(const ColGeom& g, int ml) {
-    return ml < 0 ? kSolid + g.colbase : (unsigned)ml * g.lsb + g.colbase;
+    return ml < 0 ? oadd(kSolid, g.colbase) : (unsigned)ml * g.lsb + g.colbase;
 }
 
 // Species 1 (c = 1) at layer m: exact shift.  f_a(O) = f~_a(O - c_a), or
@@ -317,6 +327,13 @@ __device__ __forceinline__ void shift_layer(const Buf& B, const GatherConst& G, 
     }
 }
 
+// wall sides of the node at layer m along the lattice axes x, y, z (-1: next
+// to the low wall, +1: next to the high wall, 0: not next to a wall)
+struct Sides {
+    int s[3];
+    bool any;
+};
+
 // Marching state of one heavier species: the marching-axis partial sums of
 // its deviation planes and the reference stencil of layers m-1, m, m+1.
 template <int LAT>
@@ -358,7 +375,7 @@ __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, 
 template <int LAT, class NB>
 __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int pb0, const float* L, unsigned own, unsigned nxt,
-                                            int side, Heavy<LAT>& h, float& P0,
+                                            const Sides& sd, Heavy<LAT>& h, float& P0,
                                             float (&F)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
@@ -375,7 +392,7 @@ __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, 
     if constexpr (DIM == 3) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const unsigned rr = own + (j == 0 ? col.bym : col.byp);
+            const unsigned rr = oadd(own, j == 0 ? col.bym : col.byp);
             float cm, cc, cp;
             nb.trip(B, pb0, rr, col, cm, cc, cp);
             cxm[j] = cm - cc;
@@ -430,29 +447,57 @@ __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, 
     // impermeable walls (Appendix A): for a pointing away from the wall,
     // f_a(O) += lambda_+1(c) f~_a(O) + lambda_-1(c) f~_abar(O); with
     // f~ = (w/w_0) P0 + g and w_a = w_abar the reference part is
-    // (w_a/w_0)(lambda_+1 + lambda_-1) P0(O).
-    if (side != 0) {
-        const int axis = G.wall_axis;
+    // (w_a/w_0)(lambda_+1 + lambda_-1) P0(O).  Where walls meet, what the
+    // node's populations would stream beyond the walls returns to the node,
+    // split by the set of walls crossed: into the reversed direction if the
+    // population moves toward one of them, else into its own direction.
+    // For a direction pointing away from n_away of the node's walls and
+    // toward n_tow of them that gives
+    //   f_a += (1 - (1 - l+)^n_away) (1 - l-)^n_tow f~_a
+    //        + (1 - (1 - l-)^n_away) f~_abar,
+    // (l+- = lambda_+-1(c)), the Appendix A terms for a single wall.
+    if (sd.any) {
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
-            const int ca = Fr::comp(a, axis);
-            if (side * ca < 0) {
-                const float ga = ldb(B, pb0 + a, own);
-                const float gb = ldb(B, pb0 + La::opp(a), own);
-                F[a] += fmaf(L[2], ga, L[0] * gb) + La::wr(a) * (L[2] + L[0]) * rc;
+            int na = 0, nt = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int p = sd.s[ax] * (ax == 0 ? La::cx(a) : (ax == 1 ? La::cy(a) : La::cz(a)));
+                na += p < 0;
+                nt += p > 0;
             }
+            if (na == 0) continue;
+            float c1 = L[2], c2 = L[0];
+            if (na > 1 || nt > 0) {
+                const float u0 = 1.0f - L[0], u2 = 1.0f - L[2];
+                float p0a = u0, p2a = u2, p0t = 1.0f;
+                for (int k = 1; k < na; ++k) {
+                    p0a *= u0;
+                    p2a *= u2;
+                }
+                for (int k = 0; k < nt; ++k) p0t *= u0;
+                c1 = (1.0f - p2a) * p0t;
+                c2 = 1.0f - p0a;
+            }
+            const float ga = ldb(B, pb0 + a, own);
+            const float gb = ldb(B, pb0 + La::opp(a), own);
+            F[a] += fmaf(c1, ga, c2 * gb) + La::wr(a) * (c1 + c2) * rc;
         }
     }
     h.rl[0] = h.rl[1];
     h.rl[1] = h.rl[2];
 }
 
-// wall side of layer m on the column's wall axis
 template <int LAT>
-__device__ __forceinline__ int wall_side(const GatherConst& G, const ColGeom& g, int m) {
+__device__ __forceinline__ Sides wall_sides(const GatherConst& G, const ColGeom& g, int m) {
+    constexpr int DIM = Lat<LAT>::DIM;
     const int sm = g.wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
-    const int axis = G.wall_axis;
-    return axis == 0 ? g.sx : (axis == Frame<LAT>::MA ? sm : g.sy);
+    Sides r;
+    r.s[0] = g.sx;
+    r.s[1] = DIM == 2 ? sm : g.sy;
+    r.s[2] = DIM == 3 ? sm : 0;
+    r.any = (r.s[0] | r.s[1] | r.s[2]) != 0;
+    return r;
 }
 
 // Forward pull gather of one column through layers [m0, m1), all species;
@@ -470,12 +515,12 @@ __device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x,
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
         const unsigned nxt = layer_off(g, mp);
-        const int side = wall_side<LAT>(G, g, m);
+        const Sides sd = wall_sides<LAT>(G, g, m);
         float P0[NS], F[NS][Q];
         shift_layer<LAT>(B, G, g, m, own, P0[0], F[0]);
 #pragma unroll
         for (int s = 1; s < NS; ++s)
-            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, side, h[s - 1], P0[s], F[s], nb);
+            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, sd, h[s - 1], P0[s], F[s], nb);
         op(P0, F, m, own);
     }
 }
@@ -495,7 +540,7 @@ __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, in
         if (s == 0)
             shift_layer<LAT>(B, G, g, m, own, P0, F);
         else
-            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_side<LAT>(G, g, m), h, P0, F, nb);
+            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_sides<LAT>(G, g, m), h, P0, F, nb);
         op(P0, F, m, own);
     }
 }
@@ -535,7 +580,7 @@ __device__ __forceinline__ bool tile_column(const Tile& T, const LatParams& P, i
     const bool inside = x < P.nx && (DIM == 2 || y < P.ny);
     zero = false;
     if (x >= P.nx) {
-        if (P.wall_axis == 0) {
+        if (P.wall_mask & 1) {
             x = P.nx - 1;
             zero = true;
         } else {

@@ -58,7 +58,7 @@ __device__ __forceinline__ void species_grads(const float* dens, const LatParams
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const float* f = dens + s * nodes;
-        field_grad<DIM>([&](int64_t j) { return f[j]; }, P.nx, P.ny, P.nz, P.wall_axis, x,
+        field_grad<DIM>([&](int64_t j) { return f[j]; }, P.nx, P.ny, P.nz, P.wall_mask, x,
                         DIM == 2 ? m : y, DIM == 2 ? 0 : m, gi[s]);
     }
 }
@@ -153,7 +153,7 @@ struct SplitOp {
         Grads gd{};
         if constexpr (FRC == 2) {
             const float* f = dens;
-            field_grad<DIM>([&](int64_t j) { return f[j]; }, P->nx, P->ny, P->nz, P->wall_axis,
+            field_grad<DIM>([&](int64_t j) { return f[j]; }, P->nx, P->ny, P->nz, P->wall_mask,
                             x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, gd.gi);
             xgr[m & 1][s][lane] = make_float4(gd.gi[0], gd.gi[1], gd.gi[2], 0.0f);
         }
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(256) k_init(const LatParams* __restrict__ lps,
                 const double sc = (double)P.M[s] * (double)P.n0;
                 const double* xs = xl + s * nodes;
                 field_grad<Lat<LAT>::DIM>([&](int64_t j) { return (float)(xs[j] * sc); }, P.nx,
-                                          P.ny, P.nz, P.wall_axis, x, y, z, gi[s]);
+                                          P.ny, P.nz, P.wall_mask, x, y, z, gi[s]);
             }
         }
         if (!collide<LAT, NS, FRC>(P0, F, C, g, gi, false, WallMove{}))   // f(0): not streamed

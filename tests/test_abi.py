@@ -97,7 +97,7 @@ def test_check_accepts_valid_problem_and_layout():
 @pytest.mark.parametrize("mutate,status", [
     (dict(tau1=0.5), 1),
     (dict(masses=[28.0, 2.0, 44.0]), 1),
-    (dict(walls=(True, True, False)), 2),
+    (dict(walls=(True, True, False), wall_velocity=[[0, 0.01, 0], [0, 0, 0]]), 2),
     (dict(lattice="D2Q9", nz=2), 1),
     (dict(nx=1), 1),
 ])

@@ -325,3 +325,27 @@ def test_adjoint_rejects_the_diffusion_forcing():
     sim.step(2)
     sim.sync()
     sim.close()
+
+
+def test_adjoint_rejects_walls_on_several_axes():
+    """Boxes with walls on two axes step forward (edges and corners are
+    handled), but the reverse step covers walls on one axis only: the adjoint
+    entry points return UNSUPPORTED."""
+    import dataclasses
+    lbm = _lbm()
+    w = dataclasses.replace(CASES[0], walls=[True, True, False])
+    _announce(f"adjoint rejects walls on two axes {w.name}")
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    sim.step(2)
+    s_prev = sim.buffers()[0].clone()
+    lam_in = torch.zeros_like(s_prev)
+    lam_out = torch.zeros_like(s_prev)
+    grad = torch.zeros(w.n_species * (w.n_species - 1) // 2 + 3, dtype=torch.float64,
+                       device=s_prev.device)
+    from paper_2504_07059_amd._lib import LbmError
+    with pytest.raises(LbmError) as e:
+        sim.adjoint_step(s_prev, lam_in, lam_out, grad)
+    assert e.value.status == 2 and "several axes" in str(e.value)
+    sim.step(2)
+    sim.sync()
+    sim.close()

@@ -66,3 +66,45 @@ def test_closed_box_at_rest_stays_at_rest_at_unit_speed(lattice, shape, walls):
     f = evd.initial_populations(m, x.clone())
     g = evd.step(m, f)
     assert (g - f).abs().max() < 1e-15
+
+
+@pytest.mark.parametrize("lattice,shape,walls", BOXES)
+def test_per_direction_closed_form_equals_the_sum_over_crossed_wall_sets(lattice, shape, walls):
+    """The kernel evaluates the rule per direction a in closed form: with
+    n_away walls of the node that a points away from and n_tow that it points
+    toward, f_a gains (1 - (1 - l+)^n_away)(1 - l-)^n_tow f~_a
+    + (1 - (1 - l-)^n_away) f~_abar (l+- = lambda_{+-1}(c), the Lagrange weights
+    of the node beyond and behind for Courant number c).  Checked here against
+    the oracle's sum over the sets of crossed walls at every node of a box,
+    for species of three speeds."""
+    m = _box(lattice, [1.0, 3.0, 7.0], shape, walls)
+    lat = m.lat
+    e = m.velocities()
+    lam = [[[evd.lagrange_weights(float(e[i, al, a])) for a in range(3)]
+            for al in range(lat.Q)] for i in range(m.N)]
+    walled = [a for a in range(3) if walls[a]]
+    gen = torch.Generator().manual_seed(3)
+    ft = torch.rand(m.N, lat.Q, m.nz, m.ny, m.nx, generator=gen, dtype=DTYPE)
+    got = evd._wall_returns(m, ft, lam, walled)
+    want = torch.zeros_like(ft)
+    dims = (m.nx, m.ny, m.nz)
+    for i in range(m.N):
+        c = max(abs(float(v)) for v in e[i].flatten())
+        lm, _, lp = evd.lagrange_weights(c)      # l- = lambda_-1(c), l+ = lambda_+1(c)
+        for z in range(m.nz):
+            for y in range(m.ny):
+                for x in range(m.nx):
+                    pos = (x, y, z)
+                    side = [0, 0, 0]
+                    for a in walled:
+                        side[a] = -1 if pos[a] == 0 else (1 if pos[a] == dims[a] - 1 else 0)
+                    for a in range(1, lat.Q):
+                        na = sum(1 for k in range(3) if side[k] * lat.dirs[a][k] < 0)
+                        nt = sum(1 for k in range(3) if side[k] * lat.dirs[a][k] > 0)
+                        if na == 0:
+                            continue
+                        c1 = (1 - (1 - lp) ** na) * (1 - lm) ** nt
+                        c2 = 1 - (1 - lm) ** na
+                        want[i, a, z, y, x] = (c1 * ft[i, a, z, y, x]
+                                               + c2 * ft[i, lat.opp[a], z, y, x])
+    assert (got - want).abs().max() < 1e-15
