@@ -65,7 +65,7 @@ typedef enum lbm_mc_status {
 } lbm_mc_status;
 
 enum { LBM_MC_D2Q9 = 0, LBM_MC_D3Q19 = 1 };
-enum { LBM_MC_PERIODIC = 0, LBM_MC_WALL = 1 };
+enum { LBM_MC_PERIODIC = 0, LBM_MC_WALL = 1, LBM_MC_WALL_EQ = 2 };
 
 /* Problem statement of one lattice. */
 typedef struct lbm_mc_params {
@@ -80,7 +80,16 @@ typedef struct lbm_mc_params {
                                would cross several walls returns to the node, in the
                                reversed direction if it moves toward any crossed wall,
                                else in its own (mass conserved; reading of Appendix A
-                               for corners). */
+                               for corners).
+                               LBM_MC_WALL_EQ = walls at the same place treated with the
+                               equilibrium comparison boundary of Sec. 4.1 instead: the
+                               solid nodes hold w_a rho_s of the fluid node they face and
+                               are interpolated over like fluid nodes, with no Appendix A
+                               terms.  A negative control, which does not conserve mass:
+                               every walled axis of every lattice uses the same kind,
+                               forcing 0, no wall velocity, no force field, no adjoint
+                               (else LBM_MC_ERR_UNSUPPORTED); it runs one thread per
+                               column (execution variant 0 only). */
     double molar_mass[4];   /* molar masses, non-decreasing; any unit (normalised) */
     double diff[4][4];      /* pair diffusivities D_ij in lattice units, symmetric,
                                > 0 off the diagonal; the diagonal is ignored */

@@ -56,6 +56,7 @@ class Workload:
     forcing: str = "standard"    # "standard"; "diff": plus the diffusion-driven term;
                                  # "full": the whole corrected forcing
     wall_velocity: Optional[List[List[float]]] = None   # [low, high] wall velocities
+    wall_kind: str = "appendix_a"   # or "equilibrium": the comparison boundary of Sec. 4.1
 
     @property
     def n_species(self):

@@ -14,7 +14,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_HIP, ERR_UNSTABLE, ERR_NONFINITE = range(6
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP",
                 4: "ERR_UNSTABLE", 5: "ERR_NONFINITE"}
 D2Q9, D3Q19 = 0, 1
-PERIODIC, WALL = 0, 1
+PERIODIC, WALL, WALL_EQ = 0, 1, 2
 
 
 class Params(ctypes.Structure):

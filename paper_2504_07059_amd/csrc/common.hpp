@@ -22,6 +22,7 @@ struct LatParams {
     int32_t tile_begin, tile_end;  // this lattice's range in the tile list
     int32_t forcing;               // 0: standard forcing term; 1: plus S_diff; 2: full
     int32_t moving;                // a wall of the wall axis moves (uw nonzero)
+    int32_t eqb;                   // 1: the walls are the equilibrium comparison boundary
     float uw[2][3];                // velocities of the low / high wall (tangential)
     float lam[MAXS][3];            // (lambda_-1, lambda_0, lambda_+1) at Courant +c_s;
                                    // the three floats sum to exactly 1
@@ -66,6 +67,7 @@ struct Launch {
     const float* accel;  // force field k(x), dense node fields [lattice][d][nodes], or null
                          // (the constant g of each lattice)
     int32_t moving;      // some lattice has a moving wall
+    int32_t eqb;         // the equilibrium comparison boundary (every lattice)
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };

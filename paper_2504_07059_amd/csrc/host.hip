@@ -46,6 +46,10 @@ constexpr int kBaseAlign = 64;    // floats: 256-byte lattice bases
 int q_of(int lattice) { return lattice == LBM_MC_D2Q9 ? 9 : 19; }
 int dim_of(int lattice) { return lattice == LBM_MC_D2Q9 ? 2 : 3; }
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+bool is_wall(int32_t bc) { return bc == LBM_MC_WALL || bc == LBM_MC_WALL_EQ; }
+bool lattice_has_eq(const lbm_mc_params& q) {
+    return q.bc[0] == LBM_MC_WALL_EQ || q.bc[1] == LBM_MC_WALL_EQ || q.bc[2] == LBM_MC_WALL_EQ;
+}
 
 // ------------------------------------------------------------ validation
 lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
@@ -73,19 +77,30 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
                             "lattice %d: one lattice's populations exceed 2 GiB per buffer "
                             "(%lld floats); split it or use fewer species", l, (long long)floats);
         }
-        int walls = 0;
+        int walls = 0, eq_walls = 0;
         for (int a = 0; a < 3; ++a) {
-            if (q.bc[a] != LBM_MC_PERIODIC && q.bc[a] != LBM_MC_WALL)
-                return fail(LBM_MC_ERR_INVALID, "lattice %d: bc[%d] must be PERIODIC or WALL", l, a);
-            if (q.bc[a] == LBM_MC_WALL) {
+            if (q.bc[a] != LBM_MC_PERIODIC && q.bc[a] != LBM_MC_WALL && q.bc[a] != LBM_MC_WALL_EQ)
+                return fail(LBM_MC_ERR_INVALID,
+                            "lattice %d: bc[%d] must be PERIODIC, WALL or WALL_EQ", l, a);
+            eq_walls += q.bc[a] == LBM_MC_WALL_EQ;
+            if (is_wall(q.bc[a])) {
                 ++walls;
                 const int n = a == 0 ? q.nx : (a == 1 ? q.ny : q.nz);
                 if (n < 2)
                     return fail(LBM_MC_ERR_INVALID, "lattice %d: a wall axis needs >= 2 nodes", l);
             }
         }
-        if (q.lattice == LBM_MC_D2Q9 && q.bc[2] == LBM_MC_WALL)
+        if (q.lattice == LBM_MC_D2Q9 && is_wall(q.bc[2]))
             return fail(LBM_MC_ERR_INVALID, "lattice %d: no z walls in 2-D", l);
+        if (eq_walls && eq_walls != walls)
+            return fail(LBM_MC_ERR_UNSUPPORTED,
+                        "lattice %d: WALL and WALL_EQ axes in one lattice are not provided", l);
+        if ((eq_walls > 0) != (lattice_has_eq(p[0])))
+            return fail(LBM_MC_ERR_UNSUPPORTED,
+                        "lattice %d: every lattice of a batch needs the same wall kind", l);
+        if (eq_walls && q.forcing != 0)
+            return fail(LBM_MC_ERR_UNSUPPORTED,
+                        "lattice %d: the equilibrium boundary is provided with forcing 0 only", l);
 
         const int N = q.n_species;
         for (int i = 0; i < N; ++i) {
@@ -114,7 +129,7 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
             return fail(LBM_MC_ERR_INVALID, "lattice %d: forcing must be 0, 1 or 2", l);
         if (q.forcing == 2)
             for (int a = 0; a < 3; ++a)
-                if (q.bc[a] == LBM_MC_WALL && (a == 0 ? q.nx : (a == 1 ? q.ny : q.nz)) < 3)
+                if (is_wall(q.bc[a]) && (a == 0 ? q.nx : (a == 1 ? q.ny : q.nz)) < 3)
                     return fail(LBM_MC_ERR_INVALID,
                                 "lattice %d: forcing 2 needs >= 3 nodes on the wall axis", l);
         if (q.forcing != p[0].forcing)
@@ -123,7 +138,7 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         {
             int wax = -1;
             for (int a = 0; a < 3; ++a)
-                if (q.bc[a] == LBM_MC_WALL) wax = a;
+                if (is_wall(q.bc[a])) wax = a;
             for (int k = 0; k < 2; ++k)
                 for (int a = 0; a < 3; ++a) {
                     const double v = q.wall_velocity[k][a];
@@ -136,6 +151,10 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
                     if (walls > 1)
                         return fail(LBM_MC_ERR_UNSUPPORTED,
                                     "lattice %d: moving walls need a single wall axis", l);
+                    if (eq_walls)
+                        return fail(LBM_MC_ERR_UNSUPPORTED,
+                                    "lattice %d: the equilibrium boundary has no moving walls",
+                                    l);
                     if (a == wax)
                         return fail(LBM_MC_ERR_INVALID,
                                     "lattice %d: wall velocities must be tangential", l);
@@ -555,6 +574,7 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.accel = c->accel;
     L.moving = 0;
     for (const auto& h : c->hlp) L.moving |= h.moving;
+    L.eqb = c->hlp[0].eqb;
     L.flag = c->dflag;
     L.stream = s;
     return L;
@@ -656,6 +676,9 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: moving walls are not differentiated");
     if (c->hlp[0].wall_axis > 2)
         return fail(LBM_MC_ERR_UNSUPPORTED, "adjoint: walls on several axes are not differentiated");
+    if (c->hlp[0].eqb)
+        return fail(LBM_MC_ERR_UNSUPPORTED,
+                    "adjoint: the equilibrium boundary is not differentiated");
     const size_t bytes = (size_t)c->layout.total * sizeof(float);
     if (!c->dmu) {
         HIPCHECK(hipMalloc(&c->dmu, bytes));
@@ -754,6 +777,9 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
     if (accel) {
         if ((uintptr_t)accel % 4)
             return fail(LBM_MC_ERR_INVALID, "the force field must be 4-byte aligned");
+        if (lattice_has_eq(p[0]))
+            return fail(LBM_MC_ERR_UNSUPPORTED,
+                        "a force field with the equilibrium boundary is not provided");
         for (int l = 0; l < n_lattices; ++l)
             for (int k = 0; k < 2; ++k)
                 for (int a = 0; a < 3; ++a)
@@ -819,8 +845,9 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
         P.field_base = lo.field[l];
         P.wall_axis = -1;
         P.wall_mask = 0;
+        P.eqb = lattice_has_eq(q) ? 1 : 0;
         for (int a = 0; a < 3; ++a)
-            if (q.bc[a] == LBM_MC_WALL) {
+            if (is_wall(q.bc[a])) {
                 P.wall_axis = P.wall_mask ? 3 : a;
                 P.wall_mask |= 1 << a;
             }
@@ -864,7 +891,9 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
 
     // default execution shape, or a cached autotuned one
     Tuning t = default_tuning(p, n_lattices, c->DIM, c->cus);
-    {
+    if (lattice_has_eq(p[0])) {
+        t.split = 0;   // the equilibrium boundary runs one thread per column
+    } else {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find({c->lattice, c->N, p[0].nx, p[0].ny, p[0].nz, n_lattices});
         if (it != g_tune_cache.end()) t = it->second;
@@ -1004,6 +1033,9 @@ lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* c, int32_t bx, int32_t by, int32_t r
         return fail(LBM_MC_ERR_INVALID, "block_x*block_y must be 64, 128, 192 or 256");
     if (t.split && t.bx * t.by != 64)
         return fail(LBM_MC_ERR_INVALID, "the species-split variant needs block_x*block_y = 64");
+    if (t.split && c->hlp[0].eqb)
+        return fail(LBM_MC_ERR_UNSUPPORTED,
+                    "the equilibrium boundary runs execution variant 0 only");
     if (t.rows < 1) return fail(LBM_MC_ERR_INVALID, "rows must be >= 1");
     c->tune = t;
     return build_tiles(c);
@@ -1069,6 +1101,7 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     double best = 1e300;
     Tuning bestt = c->tune;
     for (const Tuning& t : cands) {
+        if (t.split && c->hlp[0].eqb) continue;   // variant 0 only
         c->tune = t;
         lbm_mc_status st = build_tiles(c);
         if (st != LBM_MC_OK) return st;
@@ -1099,7 +1132,7 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     c->tune = bestt;
     lbm_mc_status st = build_tiles(c);
     if (st != LBM_MC_OK) return st;
-    {
+    if (!c->hlp[0].eqb) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const auto& q = c->params[0];
         g_tune_cache[{c->lattice, c->N, q.nx, q.ny, q.nz, c->L}] = bestt;

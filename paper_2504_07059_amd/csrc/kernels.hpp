@@ -288,8 +288,10 @@ __device__ __forceinline__ unsigned layer_off(const ColGeom& g, int ml) {
 // f~_abar(O) when O - c_a is solid (halfway bounce-back); written without
 // branches: a solid source reads the rest population at O itself (difference
 // 0) and the plane of the opposite direction.  (Each shifted value is a single
-// read here, so the cross-lane form would not save loads.)
-template <int LAT>
+// read here, so the cross-lane form would not save loads.)  With EQ (the
+// equilibrium comparison boundary) a solid source contributes nothing here;
+// eq_wall_terms adds what the solid node holds.
+template <int LAT, bool EQ = false>
 __device__ __forceinline__ void shift_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int m, unsigned own, float& P0,
                                             float (&F)[Lat<LAT>::Q]) {
@@ -324,6 +326,9 @@ __device__ __forceinline__ void shift_layer(const Buf& B, const GatherConst& G, 
         const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * B.pb)
                                   : src + (unsigned)((a - lo) * B.pb);
         F[a] = fmaf(La::wr(a), ldb(B, 0, sp) - r0, ldb(B, lo, sg));
+        if constexpr (EQ) {
+            if (solid) F[a] = -La::wr(a) * r0;
+        }
     }
 }
 
@@ -333,6 +338,56 @@ struct Sides {
     int s[3];
     bool any;
 };
+
+// The equilibrium comparison boundary of Sec. 4.1 (the scheme the paper sets
+// against Appendix A on the Loschmidt tube), for a node next to walls, added
+// to a gather in which solid sources contributed nothing: a source node O + k
+// beyond a wall holds the rest equilibrium w_a rho_s, rho_s the density of the
+// fluid node it faces (O + k with each component that crosses a wall set to
+// 0), and is interpolated over like any node (eq. Second_order_spatial_
+// interpolation, the tensor product in 3-D), so f_a(O) gains
+// w_a sum over solid k of Lambda_k(c_a) rho_s(k).  Densities from the stored
+// form: rho = P0/w_0 + sum_{a>0} g_a.
+template <int LAT>
+__device__ __forceinline__ void eq_wall_terms(const Buf& B, const GatherConst& G, const ColGeom& g,
+                                              int pb0, const float* L, unsigned own, int m,
+                                              const Sides& sd, float (&F)[Lat<LAT>::Q]) {
+    using Fr = Frame<LAT>;
+    using La = Lat<LAT>;
+    constexpr int Q = La::Q;
+    constexpr int DIM = La::DIM;
+    constexpr int K1 = DIM == 3 ? 1 : 0;
+    const float iw0 = 1.0f / La::w(0);
+    const int sx = sd.s[0], s1 = DIM == 3 ? sd.s[1] : 0, sm = sd.s[Fr::MA];
+    auto pick = [](const W3& w, int k) { return k < 0 ? w.m : (k > 0 ? w.p : w.z); };
+#pragma unroll
+    for (int km = -1; km <= 1; ++km)
+#pragma unroll
+        for (int k1 = -K1; k1 <= K1; ++k1)
+#pragma unroll
+            for (int kx = -1; kx <= 1; ++kx) {
+                const bool solx = kx != 0 && kx == sx;
+                const bool sol1 = k1 != 0 && k1 == s1;
+                const bool solm = km != 0 && km == sm;
+                if (!(solx || sol1 || solm)) continue;
+                // the facing fluid node: the in-lattice steps of k only
+                unsigned cl = (km != 0 && !solm) ? layer_off(g, nbr(m, km, G.nm, g.wm)) : own;
+                if (kx != 0 && !solx) cl += kx < 0 ? g.col.bxm : g.col.bxp;
+                if (k1 != 0 && !sol1) cl += k1 < 0 ? g.col.bym : g.col.byp;
+                float rho = ldb(B, pb0, cl) * iw0;
+#pragma unroll
+                for (int b = 1; b < Q; ++b) rho += ldb(B, pb0 + b, cl);
+#pragma unroll
+                for (int a = 1; a < Q; ++a) {
+                    if ((Fr::p0(a) == 0 && kx != 0) || (Fr::p1(a) == 0 && k1 != 0) ||
+                        (Fr::pm(a) == 0 && km != 0))
+                        continue;
+                    float wgt = pick(wsel(Fr::p0(a), L), kx) * pick(wsel(Fr::pm(a), L), km);
+                    if constexpr (DIM == 3) wgt *= pick(wsel(Fr::p1(a), L), k1);
+                    F[a] = fmaf(La::w(a) * wgt, rho, F[a]);
+                }
+            }
+}
 
 // Marching state of one heavier species: the marching-axis partial sums of
 // its deviation planes and the reference stencil of layers m-1, m, m+1.
@@ -372,10 +427,10 @@ __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, 
 
 // One layer of a heavier species: second-order interpolation plus the
 // impermeable-wall terms; side is the column's wall side on the wall axis.
-template <int LAT, class NB>
+template <int LAT, bool EQ = false, class NB>
 __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int pb0, const float* L, unsigned own, unsigned nxt,
-                                            const Sides& sd, Heavy<LAT>& h, float& P0,
+                                            int m, const Sides& sd, Heavy<LAT>& h, float& P0,
                                             float (&F)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
@@ -456,7 +511,9 @@ __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, 
     //   f_a += (1 - (1 - l+)^n_away) (1 - l-)^n_tow f~_a
     //        + (1 - (1 - l-)^n_away) f~_abar,
     // (l+- = lambda_+-1(c)), the Appendix A terms for a single wall.
-    if (sd.any) {
+    if constexpr (EQ) {
+        if (sd.any) eq_wall_terms<LAT>(B, G, g, pb0, L, own, m, sd, F);
+    } else if (sd.any) {
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
             int na = 0, nt = 0;
@@ -502,7 +559,7 @@ __device__ __forceinline__ Sides wall_sides(const GatherConst& G, const ColGeom&
 
 // Forward pull gather of one column through layers [m0, m1), all species;
 // calls op(P0, F, m, own) for every layer m (own: byte offset of the node).
-template <int LAT, int NS, class Op>
+template <int LAT, int NS, bool EQ = false, class Op>
 __device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x, int y, int m0,
                                       int m1, Op& op) {
     constexpr int Q = Lat<LAT>::Q;
@@ -517,10 +574,14 @@ __device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x,
         const unsigned nxt = layer_off(g, mp);
         const Sides sd = wall_sides<LAT>(G, g, m);
         float P0[NS], F[NS][Q];
-        shift_layer<LAT>(B, G, g, m, own, P0[0], F[0]);
+        shift_layer<LAT, EQ>(B, G, g, m, own, P0[0], F[0]);
+        if constexpr (EQ) {
+            if (sd.any) eq_wall_terms<LAT>(B, G, g, 0, G.lam[0], own, m, sd, F[0]);
+        }
 #pragma unroll
         for (int s = 1; s < NS; ++s)
-            heavy_layer<LAT>(B, G, g, s * Q, G.lam[s], own, nxt, sd, h[s - 1], P0[s], F[s], nb);
+            heavy_layer<LAT, EQ>(B, G, g, s * Q, G.lam[s], own, nxt, m, sd, h[s - 1], P0[s], F[s],
+                                 nb);
         op(P0, F, m, own);
     }
 }
@@ -540,7 +601,8 @@ __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, in
         if (s == 0)
             shift_layer<LAT>(B, G, g, m, own, P0, F);
         else
-            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, wall_sides<LAT>(G, g, m), h, P0, F, nb);
+            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, m, wall_sides<LAT>(G, g, m), h, P0, F,
+                             nb);
         op(P0, F, m, own);
     }
 }

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         StepOp<LAT, NS, FRC, EXT> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
                                     FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y,
                                     accel};
-        march<LAT, NS>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
+        march<LAT, NS, EXT == 3>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
     if (bad) atomicOr(flag, 1u);
@@ -479,7 +479,7 @@ struct MomOp {
     }
 };
 
-template <int LAT, int NS>
+template <int LAT, int NS, bool EQ>
 __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
                                                  const LatParams* __restrict__ lps,
                                                  const Tile* __restrict__ tiles, int direct,
@@ -524,7 +524,8 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
             }
         } else {
             const GatherConst G = gather_const(P, DIM);
-            march<LAT, NS>(make_buf(lb, P.plane * NS * Q, P.plane), G, x, y, T.m0, T.m1, op);
+            const Buf B = make_buf(lb, P.plane * NS * Q, P.plane);
+            march<LAT, NS, EQ>(B, G, x, y, T.m0, T.m1, op);
         }
     }
     // block reduction: wave shuffles, then the waves in a fixed order
@@ -571,7 +572,7 @@ __global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lp
 // ---------------------------------------------------------------- launchers
 // Calls fn(lattice, species count, forcing, extension) with the four as
 // compile-time constants; extension 0: constant g and resting walls, 1: a
-// force field, 2: moving walls.
+// force field, 2: moving walls, 3: the equilibrium comparison boundary.
 template <typename Fn>
 static hipError_t by_shape(int lattice, int ns, int frc, int ext, Fn&& fn) {
     using std::integral_constant;
@@ -579,6 +580,7 @@ static hipError_t by_shape(int lattice, int ns, int frc, int ext, Fn&& fn) {
         if (ext == 0) return fn(lat, n, f, integral_constant<int, 0>{});
         if (ext == 1) return fn(lat, n, f, integral_constant<int, 1>{});
         if (ext == 2) return fn(lat, n, f, integral_constant<int, 2>{});
+        if (ext == 3) return fn(lat, n, f, integral_constant<int, 3>{});
         return hipErrorInvalidValue;
     };
     auto with_frc = [&](auto lat, auto n) -> hipError_t {
@@ -600,31 +602,44 @@ static hipError_t by_shape(int lattice, int ns, int frc, int ext, Fn&& fn) {
 
 hipError_t launch_step(int lattice, int ns, const Launch& L) {
     if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
-    return by_shape(lattice, ns, L.forcing, L.accel ? 1 : (L.moving ? 2 : 0),
-                    [&](auto lat, auto n, auto frc, auto ex) {
+    return by_shape(lattice, ns, L.forcing, L.eqb ? 3 : (L.accel ? 1 : (L.moving ? 2 : 0)),
+                    [&](auto lat, auto n, auto frc, auto ex) -> hipError_t {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value, EXT = decltype(ex)::value;
-        if (FRC == 2) {
-            if (!L.dens) return hipErrorInvalidValue;
-            // (the force does not enter the densities)
+        // the equilibrium boundary: standard forcing, one thread per column
+        if constexpr (EXT == 3) {
+            if constexpr (FRC != 0) {
+                return hipErrorInvalidValue;
+            } else {
+                if (L.split) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_step<LAT, NS, 0, 3>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens,
+                                   L.accel, L.flag);
+                return hipGetLastError();
+            }
+        } else {
+            if (FRC == 2) {
+                if (!L.dens) return hipErrorInvalidValue;
+                // (the force does not enter the densities)
+                if (L.split)
+                    hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0,
+                                       L.stream, L.src, L.lp, L.tiles, L.ntiles, L.bx, L.dens);
+                else
+                    hipLaunchKernelGGL((k_density<LAT, NS>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                                       L.stream, L.src, L.lp, L.tiles, L.ntiles, L.dens);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
             if (L.split)
-                hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0,
-                                   L.stream, L.src, L.lp, L.tiles, L.ntiles, L.bx, L.dens);
+                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(64, NS), 0,
+                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
+                                   L.accel, L.flag);
             else
-                hipLaunchKernelGGL((k_density<LAT, NS>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                                   L.stream, L.src, L.lp, L.tiles, L.ntiles, L.dens);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(L.bx, L.by), 0,
+                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.accel,
+                                   L.flag);
+            return hipGetLastError();
         }
-        if (L.split)
-            hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(64, NS), 0,
-                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
-                               L.accel, L.flag);
-        else
-            hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                               L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.accel,
-                               L.flag);
-        return hipGetLastError();
     });
 }
 
@@ -638,17 +653,27 @@ hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const 
                     [&](auto la, auto n, auto frc, auto ex) {
         constexpr int LAT = decltype(la)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value, EXT = decltype(ex)::value;
-        hipLaunchKernelGGL((k_init<LAT, NS, FRC, EXT>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           lp, lat, x0, accel, f0, ft, flag);
-        return hipGetLastError();
+        if constexpr (EXT >= 2) {
+            return hipErrorInvalidValue;   // (not requested: no streaming at init)
+        } else {
+            hipLaunchKernelGGL((k_init<LAT, NS, FRC, EXT>), dim3((unsigned)blocks), dim3(256), 0,
+                               s, lp, lat, x0, accel, f0, ft, flag);
+            return hipGetLastError();
+        }
     });
 }
 
 template <int LAT, int NS>
 static hipError_t launch_moments_t(const Launch& L, int direct, float* rho, float* x, float* u,
                                    double* partial, int nq) {
-    hipLaunchKernelGGL((k_moments<LAT, NS>), dim3(L.ntiles), dim3(L.bx, L.by), 0, L.stream, L.src,
-                       L.lp, L.tiles, direct, L.accel, rho, x, u, partial, nq);
+    if (L.eqb)
+        hipLaunchKernelGGL((k_moments<LAT, NS, true>), dim3(L.ntiles), dim3(L.bx, L.by), 0,
+                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, partial,
+                           nq);
+    else
+        hipLaunchKernelGGL((k_moments<LAT, NS, false>), dim3(L.ntiles), dim3(L.bx, L.by), 0,
+                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, partial,
+                           nq);
     return hipGetLastError();
 }
 

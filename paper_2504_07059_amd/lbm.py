@@ -15,12 +15,14 @@ LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
 
 
 def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
-                walls=(False, False, False), n0=0.0, forcing=0, wall_velocity=None):
+                walls=(False, False, False), n0=0.0, forcing=0, wall_velocity=None,
+                wall_kind="appendix_a"):
     """Fill one lbm_mc_params struct (forcing: 0 or "standard" for the
     standard forcing term, 1 or "diff" to add the diffusion-driven term, 2 or
     "full" for the whole corrected forcing, - S_p + S_rho + S_diff;
     wall_velocity: optional [[low], [high]] tangential velocities of the two
-    walls of the wall axis)."""
+    walls of the wall axis; wall_kind: "appendix_a" for the impermeable walls
+    of Appendix A, "equilibrium" for the comparison boundary of Sec. 4.1)."""
     p = Params()
     p.lattice = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}[lattice] if isinstance(lattice, str) \
         else int(lattice)
@@ -28,7 +30,8 @@ def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
     N = len(masses)
     p.n_species = N
     for a in range(3):
-        p.bc[a] = _lib.WALL if walls[a] else _lib.PERIODIC
+        p.bc[a] = ({"appendix_a": _lib.WALL, "equilibrium": _lib.WALL_EQ}[wall_kind]
+                   if walls[a] else _lib.PERIODIC)
     for i in range(N):
         p.molar_mass[i] = float(masses[i])
         for j in range(N):
@@ -48,7 +51,7 @@ def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
 
 def params_from_workload(w):
     return make_params(w.lattice, w.nx, w.ny, w.nz, w.masses, w.diff, w.tau1, w.g,
-                       w.walls, w.n0 or 0.0, w.forcing, w.wall_velocity)
+                       w.walls, w.n0 or 0.0, w.forcing, w.wall_velocity, w.wall_kind)
 
 
 def _arr(params):

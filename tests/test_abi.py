@@ -237,3 +237,43 @@ def test_check_wall_velocities():
                                  ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
                                  ctypes.byref(ctx))
     assert st == 2 and b"moving walls" in L.lib.lbm_mc_last_error()
+
+
+def test_check_equilibrium_boundary_kind():
+    """bc = WALL_EQ selects the equilibrium comparison boundary (Sec. 4.1):
+    accepted on any wall axes with the standard forcing; mixing it with
+    Appendix A walls in one lattice or across a batch, the corrected
+    forcing, wall velocities and a force field are rejected (UNSUPPORTED),
+    the last before any device work."""
+    from paper_2504_07059_amd.lbm import check_problem
+    for walls in ((True, False, False), (False, True, False), (True, True, False)):
+        p = _tube(walls=walls, wall_kind="equilibrium")
+        st, _, msg = check_problem(p, _x0(p))
+        assert st == 0, (walls, msg)
+        assert list(p.bc) == [2 if w else 0 for w in walls]
+    p = _tube(walls=(True, True, False), wall_kind="equilibrium")
+    p.bc[1] = 1
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 2 and "WALL_EQ" in msg
+    a, b = _tube(wall_kind="equilibrium"), _tube()
+    st, _, msg = check_problem([a, b], np.concatenate([_x0(a), _x0(b)]))
+    assert st == 2 and "wall kind" in msg
+    p = _tube(wall_kind="equilibrium", forcing=1)
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 2 and "forcing 0" in msg
+    p = _tube(wall_kind="equilibrium", wall_velocity=[[0, 0.01, 0], [0, 0, 0]])
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 2 and "moving" in msg
+    p.bc[0] = 3
+    st, _, msg = check_problem(p, _x0(p))
+    assert st == 1 and "WALL_EQ" in msg
+    L = _lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    ctx = ctypes.c_void_p()
+    q = _tube(g=(0.0, 0.0, 0.0), wall_kind="equilibrium")
+    x = np.ascontiguousarray(_x0(q))
+    arr = (L.Params * 1)(q)
+    st = L.lib.lbm_mc_init_field(arr, 1, x.ctypes.data_as(dp), ctypes.c_void_p(1 << 20),
+                                 ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10 ** 6, None,
+                                 ctypes.byref(ctx))
+    assert st == 2 and b"equilibrium" in L.lib.lbm_mc_last_error() and not ctx.value

@@ -1,7 +1,8 @@
 """Full-size GPU parity of the optional physics on the 16384 x 1024 ternary
 tube, the lattice `bench.py` times them on: the diffusion-driven forcing
 term (forcing 1), the whole corrected forcing (forcing 2) and a force field
-k(x) in place of g, each in both execution variants.
+k(x) in place of g, each in both execution variants; and the equilibrium
+comparison boundary in place of the Appendix A walls.
 
 The lattice is too large for the FP64 oracle to run whole, so sampled nodes
 are checked after a few steps against the oracle run on a crop around each
@@ -105,6 +106,41 @@ def test_full_tube_sampled_nodes_match_oracle_crops(forcing, field, shape):
                       torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g, walls=(True, False, False),
                       force_field=ff, forcing=forcing)
         f = evd.run(m, evd.initial_populations(m, torch.tensor(sub, dtype=DTYPE)), STEPS)
+        ref = evd.collide(m, f)[:, :, 0, cy, cx]                      # [N, Q]
+        s = got[k]
+        pop = (WTS / WTS[0])[None, :] * s[:, :1] + s
+        pop[:, 0] = s[:, 0]
+        err = ((pop - ref).abs().max() / ref.abs().max()).item()
+        assert err < F_RTOL, (c, err)
+
+
+def test_full_tube_equilibrium_boundary_sampled_nodes_match_oracle_crops():
+    """The equilibrium comparison boundary on the same tube, at the shape
+    `bench.py` times it with (one thread per column, 256-column tiles of 32
+    layers), against the oracle's evd.stream_equilibrium_walls on crops (the
+    solid nodes' values depend on the fluid node next to them, so influence
+    still spreads one node per step and the crops of radius 2 s + 2 are exact
+    at their centres)."""
+    w = dataclasses.replace(_tube(), wall_kind="equilibrium")
+    _announce(f"{w.name} equilibrium boundary")
+    lbm = _lbm()
+    x0 = w.x0()
+    sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
+    sim.set_tuning(256, 1, 32, 0, 0)
+    sim.step(STEPS)
+    raw = sim.raw("cur")
+    pts = _samples(w)
+    got = torch.stack([raw[:, :, 0, y, x] for (x, y) in pts]).double().cpu()   # [P, N, Q]
+    sim.sync()
+    sim.close()
+    R = 2 * STEPS + 2
+    for k, c in enumerate(pts):
+        sub, _, (cy, cx) = _crop(w, x0, None, c, R)
+        m = evd.Model("D2Q9", sub.shape[3], sub.shape[2], 1, w.masses,
+                      torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g, walls=(True, False, False))
+        f = evd.initial_populations(m, torch.tensor(sub, dtype=DTYPE))
+        for _ in range(STEPS):
+            f = evd.stream_equilibrium_walls(m, evd.collide(m, f))
         ref = evd.collide(m, f)[:, :, 0, cy, cx]                      # [N, Q]
         s = got[k]
         pop = (WTS / WTS[0])[None, :] * s[:, :1] + s
