@@ -92,3 +92,61 @@ def test_full_batch_of_512_tubes_properties():
         x = sim.field(out, "x", l)[:, 0]                 # [N, ny, nx]
         assert torch.equal(x, x[:, :1, :].expand_as(x)), l
         assert float(x.min()) >= 0.0 and float(x.max()) <= 1.0
+
+
+def _mixed_walls(tubes):
+    """The same tubes with walls on x and y (boxes) for every other one."""
+    import dataclasses
+    return [dataclasses.replace(w, walls=[True, True, False]) if i % 2 else w
+            for i, w in enumerate(tubes)]
+
+
+@pytest.mark.parametrize("one_launch,persistent,variant", [(1, 0, 1), (1, 96, 0), (0, 0, 1)])
+def test_batch_of_boxes_and_tubes_equals_single_runs(one_launch, persistent, variant):
+    """A batch mixing tubes (x walls) and boxes (walls on x and y, with
+    corners) keeps every lattice bit-identical to its run alone: the wall
+    mask is per lattice."""
+    tubes = _mixed_walls([W.batched_tubes(count=40)[i] for i in (2, 7, 11, 19, 29)])
+    _announce(f"batch of boxes and tubes one_launch={one_launch} persistent={persistent} "
+              f"variant={variant}")
+    lbm = _lbm()
+    sim = _batch(tubes, block_x=64, rows=8, persistent=persistent, variant=variant)
+    sim.set_batched_mode(one_launch)
+    m0 = sim.moments(fields=False)["mass"].copy()
+    sim.step(41)
+    sim.sync()
+    for l, w in enumerate(tubes):
+        one = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        one.set_tuning(block_x=64, rows=8, variant=variant)
+        one.step(41)
+        one.sync()
+        assert torch.equal(sim.raw("cur", l), one.raw("cur")), (l, w.walls)
+        one.close()
+    m1 = sim.moments(fields=False)["mass"]
+    sim.sync()
+    sim.close()
+    assert np.abs(m1 / m0 - 1).max() < MASS_TOL
+
+
+@pytest.mark.parametrize("one_launch,persistent", [(1, 0), (1, 96), (0, 0)])
+def test_batch_with_the_equilibrium_boundary_equals_single_runs(one_launch, persistent):
+    """The equilibrium comparison boundary in a batch (every lattice with it,
+    as the library requires; tubes and boxes mixed), one thread per column:
+    bit-identical to each lattice run alone."""
+    import dataclasses
+    tubes = [dataclasses.replace(w, wall_kind="equilibrium")
+             for w in _mixed_walls([W.batched_tubes(count=40)[i] for i in (3, 8, 21, 33)])]
+    _announce(f"equilibrium-boundary batch one_launch={one_launch} persistent={persistent}")
+    lbm = _lbm()
+    sim = _batch(tubes, block_x=64, rows=8, persistent=persistent, variant=0)
+    sim.set_batched_mode(one_launch)
+    sim.step(29)
+    sim.sync()
+    for l, w in enumerate(tubes):
+        one = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        one.set_tuning(block_x=64, rows=8, variant=0)
+        one.step(29)
+        one.sync()
+        assert torch.equal(sim.raw("cur", l), one.raw("cur")), (l, w.walls)
+        one.close()
+    sim.close()
