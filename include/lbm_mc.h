@@ -10,7 +10,8 @@
  * (Table 2), a viscosity set through tau_1 (Sec. 4 opening), a body force on
  * each species F_i = rho_i g (eq. MS_equation with k_i = g; Sec. 4.1), an
  * initial composition x_i(x) with a total mole number n0 (Sec. 4.1), and
- * impermeable walls (Appendix A) or periodicity on each axis.  The caller
+ * impermeable walls (Appendix A) or periodicity on each axis (and, as the
+ * paper's comparison case, the equilibrium boundary of Sec. 4.1).  The caller
  * advances the system and observes x_i, rho_i, u and the total mass of every
  * species (Sec. 4.1: region-averaged mole fractions, total mass).
  *
