@@ -56,6 +56,8 @@ CASES = [
         (0, 0, 1e-5), 12),
     _wk("d3q19_n2_xz_box", "D3Q19", (20, 9, 11), [1.0, 5.0], (True, False, True),
         (2e-5, 0, 1e-5), 12),
+    _wk("d3q19_n4_xyz_box", "D3Q19", (19, 10, 9), [1.0, 2.0, 3.0, 4.0], (True, True, True),
+        (1e-5, -1e-5, 1e-5), 10),
 ]
 
 
@@ -72,6 +74,8 @@ def _oracle_run(m, f, steps):
 
 @pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
 def test_equilibrium_boundary_matches_oracle(w):
+    """Against evd.stream_equilibrium_walls: 2-D walls on x, y and both,
+    3-D walls on z, on x and z, and on all three axes, 2-4 species."""
     _announce(f"equilibrium boundary {w.name}")
     lbm = _lbm()
     m = _model(w)
