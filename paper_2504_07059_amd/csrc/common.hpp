@@ -68,6 +68,8 @@ struct Launch {
                          // (the constant g of each lattice)
     int32_t moving;      // some lattice has a moving wall
     int32_t eqb;         // the equilibrium comparison boundary (every lattice)
+    int32_t wt;          // store populations written through (both buffers fit in the
+                         // last-level cache), else non-temporal
     unsigned* flag;      // sticky error flags (bit 0: non-finite)
     hipStream_t stream;
 };

@@ -575,6 +575,10 @@ Launch make_launch(lbm_mc_ctx* c, const float* src, float* dst, hipStream_t s) {
     L.moving = 0;
     for (const auto& h : c->hlp) L.moving |= h.moving;
     L.eqb = c->hlp[0].eqb;
+    // both population buffers within the 256 MB last-level cache: the stores
+    // write through to it (the next step reads them back from there); above
+    // it they stream past the caches
+    L.wt = 2 * c->layout.total * (int64_t)sizeof(float) <= ((int64_t)256 << 20) ? 1 : 0;
     L.flag = c->dflag;
     L.stream = s;
     return L;

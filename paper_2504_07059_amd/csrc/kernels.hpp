@@ -79,14 +79,19 @@ __device__ __forceinline__ float ldb(const Buf& b, int p, unsigned vb) {
     return __builtin_bit_cast(
         float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)vb, p * b.pb, 0));
 }
-// Populations are stored with the non-temporal cache policy (the `nt` bit):
-// a launch writes every value once and reads none of them back.  Measured, it
-// takes 5 % off the step on lattices larger than the caches and 2 % on a
-// cache-resident one; it changes no value and no coherence rule.
+// Cache policy of the population stores (a launch writes every value once
+// and reads none of them back).  kStoreNT, the non-temporal (`nt`) policy,
+// suits states larger than the last-level cache; kStoreWT, device scope
+// (`sc1`: written through to the last-level cache), suits states that fit in
+// it and are read again from there by the next step.  Either changes no value
+// and no coherence rule; the host picks one per context by the size of the
+// two population buffers.
 constexpr int kStoreNT = 2;
+constexpr int kStoreWT = 16;
+template <int POL = kStoreNT>
 __device__ __forceinline__ void stb(const Buf& b, int p, unsigned vb, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, (int)vb,
-                                          p * b.pb, kStoreNT);
+                                          p * b.pb, POL);
 }
 
 // Neighbour index i+k on an axis of n nodes: wrapped when periodic, -1 when the

@@ -63,7 +63,7 @@ __device__ __forceinline__ void species_grads(const float* dens, const LatParams
     }
 }
 
-template <int LAT, int NS, int FRC, int EXT>
+template <int LAT, int NS, int FRC, int EXT, int POL>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -85,14 +85,14 @@ struct StepOp {
         if (!collide<LAT, NS, FRC>(P0, F, C, g, gi, mw, W)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            stb(D, s * Q, own, P0[s]);
+            stb<POL>(D, s * Q, own, P0[s]);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) stb(D, s * Q + a, own, F[s][a]);
+            for (int a = 1; a < Q; ++a) stb<POL>(D, s * Q + a, own, F[s][a]);
         }
     }
 };
 
-template <int LAT, int NS, int FRC, int EXT>
+template <int LAT, int NS, int FRC, int EXT, int POL>
 __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, float* __restrict__ dst,
                                               const LatParams* __restrict__ lps,
                                               const Tile* __restrict__ tiles, int ntiles,
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS, FRC, EXT> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
+        StepOp<LAT, NS, FRC, EXT, POL> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
                                     FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y,
                                     accel};
         march<LAT, NS, EXT == 3>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, so several times more waves fit on a SIMD.
-template <int LAT, int NS, int FRC, int EXT>
+template <int LAT, int NS, int FRC, int EXT, int POL>
 struct SplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
@@ -204,15 +204,15 @@ struct SplitOp {
         const bool ok = collide_species<LAT, FRC>(K, g, rho_s, dlt_s, ue_s, M, V, gd, P0, F) &&
                         isfinite(M.R);
         if (inside) {
-            stb(D, s * Q, own, P0);
+            stb<POL>(D, s * Q, own, P0);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) stb(D, s * Q + a, own, F[a]);
+            for (int a = 1; a < Q; ++a) stb<POL>(D, s * Q + a, own, F[a]);
             bad = bad || !ok;
         }
     }
 };
 
-template <int LAT, int NS, int FRC, int EXT>
+template <int LAT, int NS, int FRC, int EXT, int POL>
 __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
                                                     float* __restrict__ dst,
                                                     const LatParams* __restrict__ lps,
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         // the species' own constants, read with the uniform species index
         // (scalar loads; no run-time indexing of register arrays)
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-        SplitOp<LAT, NS, FRC, EXT> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+        SplitOp<LAT, NS, FRC, EXT, POL> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
                                               P.kdiff[s], P.cs2[s]},
                                  xch, reinterpret_cast<float4 (*)[NS][64]>(xgr), s, lane,
@@ -612,9 +612,14 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
                 return hipErrorInvalidValue;
             } else {
                 if (L.split) return hipErrorInvalidValue;
-                hipLaunchKernelGGL((k_step<LAT, NS, 0, 3>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens,
-                                   L.accel, L.flag);
+                if (L.wt)
+                    hipLaunchKernelGGL((k_step<LAT, NS, 0, 3, kStoreWT>), dim3(L.grid),
+                                       dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                       L.ntiles, L.dens, L.accel, L.flag);
+                else
+                    hipLaunchKernelGGL((k_step<LAT, NS, 0, 3, kStoreNT>), dim3(L.grid),
+                                       dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                       L.ntiles, L.dens, L.accel, L.flag);
                 return hipGetLastError();
             }
         } else {
@@ -630,14 +635,22 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
-            if (L.split)
-                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(64, NS), 0,
-                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.bx, L.dens,
-                                   L.accel, L.flag);
+            if (L.split && L.wt)
+                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, kStoreWT>), dim3(L.grid),
+                                   dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                   L.ntiles, L.bx, L.dens, L.accel, L.flag);
+            else if (L.split)
+                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, kStoreNT>), dim3(L.grid),
+                                   dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                   L.ntiles, L.bx, L.dens, L.accel, L.flag);
+            else if (L.wt)
+                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT, kStoreWT>), dim3(L.grid),
+                                   dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                   L.ntiles, L.dens, L.accel, L.flag);
             else
-                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT>), dim3(L.grid), dim3(L.bx, L.by), 0,
-                                   L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens, L.accel,
-                                   L.flag);
+                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT, kStoreNT>), dim3(L.grid),
+                                   dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                   L.ntiles, L.dens, L.accel, L.flag);
             return hipGetLastError();
         }
     });
