@@ -54,7 +54,7 @@ __device__ __forceinline__ void block_reduce_add(double (&acc)[NG], double* __re
 // the shared adjoints (u, rho, the densities and velocities, y); every wave
 // sums them in species order and runs the shared tail (mixture and
 // cross-relaxation reverse), then finishes and stores its own species' mu.
-template <int LAT, int NS>
+template <int LAT, int NS, int POL>
 struct AdjSplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     static constexpr int NG = NS * (NS - 1) / 2 + 3;
@@ -159,7 +159,7 @@ struct AdjSplitOp {
         }
         if (inside) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) stb(mu, s * Q + a, own, lt[a]);
+            for (int a = 0; a < Q; ++a) stb<POL>(mu, s * Q + a, own, lt[a]);
             int k = 0;
             // every wave holds the same dL/dK: the species-0 wave adds it
 #pragma unroll
@@ -172,7 +172,7 @@ struct AdjSplitOp {
     }
 };
 
-template <int LAT, int NS>
+template <int LAT, int NS, int POL>
 __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ fprev,
                                                      const float* __restrict__ lam,
                                                      float* __restrict__ mu,
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
                                                      double* __restrict__ gpart) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
-    using Op = AdjSplitOp<LAT, NS>;
+    using Op = AdjSplitOp<LAT, NS, POL>;
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
     const int lane = (int)threadIdx.x;
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
 // where X + c_a is solid.  Stored as lam_s = T^-T lam_f:
 // lam_P0 = lam_f0 + sum_a (w_a/w_0) lam_fa, lam_ga = lam_fa.  One thread per
 // (column, species): species are independent here.
-template <int LAT, int NS>
+template <int LAT, int NS, int POL>
 __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu,
                                                     float* __restrict__ lamout,
                                                     const LatParams* __restrict__ lps,
@@ -318,9 +318,9 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
             lp0 = fmaf(La::wr(a), lf_[a], lp0);
-            stb(O, pb0 + a, own, lf_[a]);
+            stb<POL>(O, pb0 + a, own, lf_[a]);
         }
-        stb(O, pb0, own, lp0);
+        stb<POL>(O, pb0, own, lp0);
     }
 }
 
@@ -435,8 +435,12 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const LatParams* __restrict
 template <int LAT, int NS>
 static hipError_t adj_t(const Launch& L, const float* lam_in, float* mu, double* gpart) {
     if (L.bx * L.by != 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_adj_collide<LAT, NS>), dim3(L.ntiles), dim3(64, NS), 0, L.stream,
-                       L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
+    if (L.wt)
+        hipLaunchKernelGGL((k_adj_collide<LAT, NS, kStoreWT>), dim3(L.ntiles), dim3(64, NS), 0,
+                           L.stream, L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
+    else
+        hipLaunchKernelGGL((k_adj_collide<LAT, NS, kStoreNT>), dim3(L.ntiles), dim3(64, NS), 0,
+                           L.stream, L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
     return hipGetLastError();
 }
 
@@ -457,8 +461,12 @@ hipError_t launch_adjoint(int lattice, int ns, const Launch& L, const float* lam
 template <int LAT, int NS>
 static hipError_t adjs_t(const Launch& L, const float* mu, float* lam_out) {
     if (L.bx * L.by != 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_adj_stream<LAT, NS>), dim3(L.ntiles), dim3(64, NS), 0, L.stream, mu,
-                       lam_out, L.lp, L.tiles, L.bx);
+    if (L.wt)
+        hipLaunchKernelGGL((k_adj_stream<LAT, NS, kStoreWT>), dim3(L.ntiles), dim3(64, NS), 0,
+                           L.stream, mu, lam_out, L.lp, L.tiles, L.bx);
+    else
+        hipLaunchKernelGGL((k_adj_stream<LAT, NS, kStoreNT>), dim3(L.ntiles), dim3(64, NS), 0,
+                           L.stream, mu, lam_out, L.lp, L.tiles, L.bx);
     return hipGetLastError();
 }
 

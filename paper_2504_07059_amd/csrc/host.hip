@@ -737,6 +737,10 @@ lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_i
     L.ntiles = L.grid = c->adj_ntiles;
     L.bx = c->adj_bx;
     L.by = c->adj_by;
+    // the reverse step keeps four population-sized buffers in play (the
+    // state, the two adjoints and the scratch): written-through stores while
+    // they fit in the last-level cache
+    L.wt = 4 * c->layout.total * (int64_t)sizeof(float) <= ((int64_t)256 << 20) ? 1 : 0;
     HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, c->dmu, c->dgpart, ng));
     HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, c->dmu, lam_out));
     return LBM_MC_OK;
