@@ -17,6 +17,8 @@
 // per work-group and then over work-groups in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "adjoint.hpp"
 #include "kernels.hpp"
 
@@ -435,12 +437,15 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const LatParams* __restrict
 template <int LAT, int NS>
 static hipError_t adj_t(const Launch& L, const float* lam_in, float* mu, double* gpart) {
     if (L.bx * L.by != 64) return hipErrorInvalidValue;
+    auto go = [&](auto pol) {
+        hipLaunchKernelGGL((k_adj_collide<LAT, NS, decltype(pol)::value>), dim3(L.ntiles),
+                           dim3(64, NS), 0, L.stream, L.src, lam_in, mu, L.lp, L.tiles, L.bx,
+                           gpart);
+    };
     if (L.wt)
-        hipLaunchKernelGGL((k_adj_collide<LAT, NS, kStoreWT>), dim3(L.ntiles), dim3(64, NS), 0,
-                           L.stream, L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
+        go(std::integral_constant<int, kStoreWT>{});
     else
-        hipLaunchKernelGGL((k_adj_collide<LAT, NS, kStoreNT>), dim3(L.ntiles), dim3(64, NS), 0,
-                           L.stream, L.src, lam_in, mu, L.lp, L.tiles, L.bx, gpart);
+        go(std::integral_constant<int, kStoreNT>{});
     return hipGetLastError();
 }
 
@@ -461,12 +466,14 @@ hipError_t launch_adjoint(int lattice, int ns, const Launch& L, const float* lam
 template <int LAT, int NS>
 static hipError_t adjs_t(const Launch& L, const float* mu, float* lam_out) {
     if (L.bx * L.by != 64) return hipErrorInvalidValue;
+    auto go = [&](auto pol) {
+        hipLaunchKernelGGL((k_adj_stream<LAT, NS, decltype(pol)::value>), dim3(L.ntiles),
+                           dim3(64, NS), 0, L.stream, mu, lam_out, L.lp, L.tiles, L.bx);
+    };
     if (L.wt)
-        hipLaunchKernelGGL((k_adj_stream<LAT, NS, kStoreWT>), dim3(L.ntiles), dim3(64, NS), 0,
-                           L.stream, mu, lam_out, L.lp, L.tiles, L.bx);
+        go(std::integral_constant<int, kStoreWT>{});
     else
-        hipLaunchKernelGGL((k_adj_stream<LAT, NS, kStoreNT>), dim3(L.ntiles), dim3(64, NS), 0,
-                           L.stream, mu, lam_out, L.lp, L.tiles, L.bx);
+        go(std::integral_constant<int, kStoreNT>{});
     return hipGetLastError();
 }
 

@@ -606,21 +606,31 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
                     [&](auto lat, auto n, auto frc, auto ex) -> hipError_t {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value, EXT = decltype(ex)::value;
-        // the equilibrium boundary: standard forcing, one thread per column
+        // the fused step with the store policy the host chose (a template
+        // argument: the policy is an immediate of the store instructions)
+        auto step = [&](auto pol) -> hipError_t {
+            constexpr int POL = decltype(pol)::value;
+            if constexpr (EXT != 3) {   // (the equilibrium boundary has no split form)
+                if (L.split) {
+                    hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, POL>), dim3(L.grid),
+                                       dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
+                                       L.ntiles, L.bx, L.dens, L.accel, L.flag);
+                    return hipGetLastError();
+                }
+            }
+            hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT, POL>), dim3(L.grid), dim3(L.bx, L.by),
+                               0, L.stream, L.src, L.dst, L.lp, L.tiles, L.ntiles, L.dens,
+                               L.accel, L.flag);
+            return hipGetLastError();
+        };
         if constexpr (EXT == 3) {
+            // the equilibrium boundary: standard forcing, one thread per column
             if constexpr (FRC != 0) {
                 return hipErrorInvalidValue;
             } else {
                 if (L.split) return hipErrorInvalidValue;
-                if (L.wt)
-                    hipLaunchKernelGGL((k_step<LAT, NS, 0, 3, kStoreWT>), dim3(L.grid),
-                                       dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                       L.ntiles, L.dens, L.accel, L.flag);
-                else
-                    hipLaunchKernelGGL((k_step<LAT, NS, 0, 3, kStoreNT>), dim3(L.grid),
-                                       dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                       L.ntiles, L.dens, L.accel, L.flag);
-                return hipGetLastError();
+                return L.wt ? step(std::integral_constant<int, kStoreWT>{})
+                            : step(std::integral_constant<int, kStoreNT>{});
             }
         } else {
             if (FRC == 2) {
@@ -635,23 +645,8 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
-            if (L.split && L.wt)
-                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, kStoreWT>), dim3(L.grid),
-                                   dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                   L.ntiles, L.bx, L.dens, L.accel, L.flag);
-            else if (L.split)
-                hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, kStoreNT>), dim3(L.grid),
-                                   dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                   L.ntiles, L.bx, L.dens, L.accel, L.flag);
-            else if (L.wt)
-                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT, kStoreWT>), dim3(L.grid),
-                                   dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                   L.ntiles, L.dens, L.accel, L.flag);
-            else
-                hipLaunchKernelGGL((k_step<LAT, NS, FRC, EXT, kStoreNT>), dim3(L.grid),
-                                   dim3(L.bx, L.by), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                   L.ntiles, L.dens, L.accel, L.flag);
-            return hipGetLastError();
+            return L.wt ? step(std::integral_constant<int, kStoreWT>{})
+                        : step(std::integral_constant<int, kStoreNT>{});
         }
     });
 }
