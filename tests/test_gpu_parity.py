@@ -255,3 +255,60 @@ def test_ternary_gravity_full_size(steps):
     assert np.abs(out["mass"][0] / m0 - 1).max() < MASS_TOL
     want = np.array(g["mass_per_row"]) * w.ny
     assert np.abs(out["mass"][0] / want - 1).max() < MASS_TOL
+
+
+def _absent_x0(w, where):
+    """Mole fractions with species 3 absent everywhere ("all") or in the low
+    half of the first axis while species 1 is absent in the high half
+    ("halves"); the rest a seeded random split."""
+    rng = np.random.default_rng(8)
+    shape = (w.nz, w.ny, w.nx)
+    x = np.zeros((3,) + shape)
+    a = rng.uniform(0.2, 0.8, size=shape)
+    if where == "all":
+        x[0], x[1] = a, 1 - a
+    else:
+        lo = np.zeros(shape, dtype=bool)
+        lo[..., : w.nx // 2] = True
+        b = rng.uniform(0.1, 0.5, size=shape)
+        x[0] = np.where(lo, a, 0.0)
+        x[1] = np.where(lo, 1 - a, b)
+        x[2] = np.where(lo, 0.0, 1 - b)
+    return x
+
+
+_D08 = [[0.0, 0.08, 0.08], [0.08, 0.0, 0.08], [0.08, 0.08, 0.0]]
+ABSENT = [("all", _wk("d2q9_n3_absent", "D2Q9", (130, 7, 1), [2.0, 28.0, 44.0],
+                      (True, False, False), (1e-5, 0, 0))),
+          ("halves", _wk("d2q9_n3_absent_halves", "D2Q9", (130, 7, 1), [2.0, 28.0, 44.0],
+                         (True, True, False), (1e-5, -1e-5, 0), diff=_D08)),
+          ("halves", _wk("d3q19_n3_absent_halves", "D3Q19", (40, 9, 11), [1.0, 2.0, 6.0],
+                         (True, False, True), (1e-5, 0, -1e-5), steps=16, diff=_D08))]
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["joint", "split"])
+@pytest.mark.parametrize("where,w", ABSENT, ids=[f"{w.name}" for _, w in ABSENT])
+def test_absent_species_match_oracle(where, w, variant):
+    """Zero densities (reading R4) with unequal masses and gravity: a species
+    absent everywhere stays exactly 0 on the GPU too, and species absent from
+    one half of the lattice meet the others at an interface, against the
+    oracle in both execution variants."""
+    _announce(f"{w.name} absent={where} variant {variant}")
+    x0 = _absent_x0(w, where)
+    m = _oracle_model(w)
+    f = evd.run(m, evd.initial_populations(m, torch.tensor(x0, dtype=DTYPE)), w.steps)
+    ob = evd.observables(m, f)
+    ft = evd.collide(m, f)
+    shape = ((64, 1, 4, 0, 1) if variant else (64, 1, 4, 0, 0)) if w.lattice == "D2Q9" \
+        else ((16, 4, 3, 0, 1) if variant else (16, 4, 3, 0, 0))
+    sim, out, m0 = _gpu_run(w, w.steps, shape, x0=x0)
+    xg = sim.field(out, "x").double().cpu()
+    fg = sim.populations("cur").double().cpu()
+    sim.close()
+    assert (xg - ob["x"]).abs().max().item() < X_TOL
+    assert ((fg - ft).abs().max() / ft.abs().max()).item() < F_RTOL
+    present = m0 > 0
+    assert np.abs(out["mass"][0][present] / m0[present] - 1).max() < MASS_TOL
+    if where == "all":
+        assert fg[2].abs().max().item() == 0.0
+        assert out["mass"][0][2] == 0.0

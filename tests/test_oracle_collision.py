@@ -250,3 +250,31 @@ def test_relaxation_matrix_predicts_uniform_evolution():
     K = stability.relaxation_matrix(m, x)
     pred = (np.eye(3) - K) @ u0 + np.array([1e-3, 0.0])[None, :]
     assert np.abs(u1 - pred).max() < 1e-15
+
+
+@pytest.mark.parametrize("lattice,shape,walls", [("D2Q9", (40, 3, 1), (True, False, False)),
+                                                 ("D3Q19", (6, 5, 7), (False, False, True))])
+def test_an_absent_species_changes_nothing(lattice, shape, walls):
+    """A species with rho_i = 0 everywhere (reading R4: u_i^eq = g/2, every
+    term it enters is multiplied by rho_i) stays exactly 0, and the others
+    evolve exactly as the mixture without it (same masses, diffusivities,
+    n0 and force): the cross collision x_s x_t (u_t - u_s)/D_st and the
+    tau relation lose every term of the absent species."""
+    nx, ny, nz = shape
+    D3 = torch.tensor([[0, 0.07, 0.05], [0.07, 0, 0.09], [0.05, 0.09, 0]], dtype=DTYPE)
+    g = [1e-5, 0.0, 0.0] if lattice == "D2Q9" else [0.0, 0.0, -1e-5]
+    rng = np.random.default_rng(6)
+    x = np.zeros((3, nz, ny, nx))
+    x[0] = rng.uniform(0.2, 0.8, size=(nz, ny, nx))
+    x[1] = 1 - x[0]
+    m3 = evd.Model(lattice, nx, ny, nz, [2.0, 28.0, 44.0], D3, 1.0, g=g, walls=walls,
+                   n0=1 / 44)
+    m2 = evd.Model(lattice, nx, ny, nz, [2.0, 28.0], D3[:2, :2].clone(), 1.0, g=g,
+                   walls=walls, n0=1 / 44)
+    f3 = evd.initial_populations(m3, torch.tensor(x, dtype=DTYPE))
+    f2 = evd.initial_populations(m2, torch.tensor(x[:2], dtype=DTYPE))
+    for _ in range(12):
+        f3 = evd.step(m3, f3)
+        f2 = evd.step(m2, f2)
+    assert f3[2].abs().max() == 0.0
+    assert (f3[:2] - f2).abs().max() < 1e-15
