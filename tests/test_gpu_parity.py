@@ -312,3 +312,38 @@ def test_absent_species_match_oracle(where, w, variant):
     if where == "all":
         assert fg[2].abs().max().item() == 0.0
         assert out["mass"][0][2] == 0.0
+
+
+TINY = [
+    _wk("d2q9_n3_one_row", "D2Q9", (70, 1, 1), [2.0, 28.0, 44.0], (True, False, False),
+        (1e-5, 0, 0), steps=30),
+    _wk("d2q9_n2_two_columns", "D2Q9", (2, 5, 1), [1.0, 3.0], (True, False, False),
+        (2e-5, 1e-5, 0), steps=30),
+    _wk("d2q9_n3_two_by_two_box", "D2Q9", (2, 2, 1), [1.0, 2.0, 5.0], (True, True, False),
+        (1e-5, -1e-5, 0), steps=30),
+    _wk("d2q9_n2_one_column_periodic", "D2Q9", (1, 6, 1), [1.0, 3.0], (False, False, False),
+        (0, 1e-5, 0), steps=30),
+    _wk("d3q19_n3_one_row", "D3Q19", (33, 1, 9), [1.0, 2.0, 6.0], (False, False, True),
+        (0, 0, -1e-5), steps=16),
+    _wk("d3q19_n2_one_layer", "D3Q19", (17, 6, 1), [1.0, 4.0], (True, False, False),
+        (1e-5, 0, 0), steps=16),
+    _wk("d3q19_n4_two_cube", "D3Q19", (2, 2, 2), [1.0, 2.0, 3.0, 4.0], (True, True, True),
+        (1e-5, 1e-5, -1e-5), steps=16),
+]
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["joint", "split"])
+@pytest.mark.parametrize("w", TINY, ids=[w.name for w in TINY])
+def test_tiny_axes_match_oracle(w, variant):
+    """Axes of one or two nodes: a periodic node that is its own neighbour,
+    walls two nodes apart (every node next to both), boxes of 2x2 and
+    2x2x2 nodes where every node is a corner, one-row and one-layer 3-D
+    lattices; against the oracle in both execution variants."""
+    _announce(f"{w.name} variant {variant}")
+    shape = ((64, 1, 4, 0, 1) if variant else (64, 1, 4, 0, 0)) if w.lattice == "D2Q9" \
+        else ((16, 4, 3, 0, 1) if variant else (16, 4, 3, 0, 0))
+    dx, df, drift, dmass = _compare(w, w.steps, tuning=shape)
+    assert dx < X_TOL, dx
+    assert df < F_RTOL, df
+    assert drift < MASS_TOL, drift
+    assert dmass < MASS_TOL, dmass
