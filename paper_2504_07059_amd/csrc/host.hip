@@ -373,6 +373,12 @@ struct Tuning {
     int bx = 256, by = 1, rows = 32, persistent = 0, split = 0;
 };
 
+// Step counts of the captured step sequences that lbm_mc_step replays, longest
+// first (both even).  A graph launch costs a few microseconds of its own,
+// which is most of a step on a small lattice: on the 1024x64 tube the step
+// takes 6.42 us with 32-step graphs and 6.25 us with 512-step ones.
+constexpr int kGraphSteps[2] = {512, 32};
+
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, Tuning> g_tune_cache;
 // (the cache key: lattice, species, nx, ny, nz of the first lattice, lattice count)
@@ -406,9 +412,8 @@ struct lbm_mc_ctx {
     const float* accel = nullptr;       // caller's force field (lbm_mc_init_field), borrowed
     int one_launch = 1;
     int cus = 256;
-    // captured step graphs (index: cur == bufA)
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int gsteps = 32;
+    // captured step sequences: [length class][which buffer is current]
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     // adjoint: scratch population-space buffer, second adjoint buffer for
     // adjoint_run, gradient partials, and the initial mole fractions (kept for
     // the initialisation VJP of single-lattice contexts)
@@ -433,10 +438,11 @@ struct lbm_mc_ctx {
 namespace {
 
 void drop_graphs(lbm_mc_ctx* c) {
-    for (auto& g : c->gexec) {
-        if (g) hipGraphExecDestroy(g);
-        g = nullptr;
-    }
+    for (auto& row : c->gexec)
+        for (auto& g : row) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     for (auto& g : c->seq_graphs) hipGraphExecDestroy(g.exec);
     c->seq_graphs.clear();
 }
@@ -600,14 +606,19 @@ lbm_mc_status launch_one(lbm_mc_ctx* c, const float* src, float* dst, hipStream_
     return LBM_MC_OK;
 }
 
-lbm_mc_status get_graph(lbm_mc_ctx* c, hipGraphExec_t* out) {
+// The long step sequences only where a step is one launch (a batch stepped
+// with one launch per lattice would put hundreds of thousands of nodes in one
+// graph).
+bool long_graphs(const lbm_mc_ctx* c) { return c->L == 1 || c->one_launch; }
+
+lbm_mc_status get_graph(lbm_mc_ctx* c, int cls, hipGraphExec_t* out) {
     const int key = c->cur == c->bufA ? 0 : 1;
-    if (!c->gexec[key]) {
+    if (!c->gexec[cls][key]) {
         HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
         float* src = c->cur;
         float* dst = c->prev;
         lbm_mc_status st = LBM_MC_OK;
-        for (int i = 0; i < c->gsteps && st == LBM_MC_OK; ++i) {
+        for (int i = 0; i < kGraphSteps[cls] && st == LBM_MC_OK; ++i) {
             st = launch_one(c, src, dst, c->cap);
             std::swap(src, dst);
         }
@@ -618,12 +629,12 @@ lbm_mc_status get_graph(lbm_mc_ctx* c, hipGraphExec_t* out) {
             return st;
         }
         if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&c->gexec[cls][key], g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e != hipSuccess)
             return fail(LBM_MC_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
     }
-    *out = c->gexec[key];
+    *out = c->gexec[cls][key];
     return LBM_MC_OK;
 }
 
@@ -953,13 +964,15 @@ lbm_mc_status lbm_mc_step(lbm_mc_ctx* c, int64_t n) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (n < 0) return fail(LBM_MC_ERR_INVALID, "n_steps must be >= 0");
     while (n > 0) {
-        if (n >= c->gsteps) {
+        const int cls = n >= kGraphSteps[0] && long_graphs(c) ? 0
+                        : (n >= kGraphSteps[1] ? 1 : -1);
+        if (cls >= 0) {
             hipGraphExec_t g;
-            lbm_mc_status st = get_graph(c, &g);
+            lbm_mc_status st = get_graph(c, cls, &g);
             if (st != LBM_MC_OK) return st;
             HIPCHECK(hipGraphLaunch(g, c->stream));
-            n -= c->gsteps;
-            c->t += c->gsteps;   // gsteps is even: cur/prev are back in place
+            n -= kGraphSteps[cls];
+            c->t += kGraphSteps[cls];   // an even count: cur/prev are back in place
         } else {
             lbm_mc_status st = launch_one(c, c->cur, c->prev, c->stream);
             if (st != LBM_MC_OK) return st;
@@ -968,6 +981,21 @@ lbm_mc_status lbm_mc_step(lbm_mc_ctx* c, int64_t n) {
             n -= 1;
         }
         c->prev_valid = true;
+    }
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_prepare(lbm_mc_ctx* c, int64_t n) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(LBM_MC_ERR_INVALID, "n_steps must be >= 0");
+    // the graph lengths are even, so lbm_mc_step replays them all with the
+    // current buffer assignment
+    for (int cls = 0; cls < 2; ++cls) {
+        if (n < kGraphSteps[cls] || (cls == 0 && !long_graphs(c))) continue;
+        hipGraphExec_t g;
+        lbm_mc_status st = get_graph(c, cls, &g);
+        if (st != LBM_MC_OK) return st;
+        n %= kGraphSteps[cls];
     }
     return LBM_MC_OK;
 }

@@ -128,6 +128,10 @@ class LbmMc:
     def step(self, n=1):
         check(lib.lbm_mc_step(self.ctx, int(n)))
 
+    def prepare(self, n):
+        """Capture ahead of time the step graphs that step(n) will replay."""
+        check(lib.lbm_mc_prepare(self.ctx, int(n)))
+
     def sync(self):
         check(lib.lbm_mc_sync(self.ctx))
 

@@ -184,6 +184,7 @@ def test_init_rejects_bad_buffers_before_touching_the_gpu():
                            ctypes.c_void_p(8192), 10, None, ctypes.byref(ctx))
     assert st == 1 and b"floats" in L.lib.lbm_mc_last_error()
     assert L.lib.lbm_mc_step(None, 1) == 1
+    assert L.lib.lbm_mc_prepare(None, 1) == 1
     assert L.lib.lbm_mc_destroy(None) == 0
 
 

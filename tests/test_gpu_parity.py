@@ -347,3 +347,31 @@ def test_tiny_axes_match_oracle(w, variant):
     assert df < F_RTOL, df
     assert drift < MASS_TOL, drift
     assert dmass < MASS_TOL, dmass
+
+
+def test_graph_lengths_and_prepare_do_not_change_results():
+    """lbm_mc_step replays captured sequences of 512 and 32 steps and single
+    launches for the rest; lbm_mc_prepare captures them ahead of time and
+    runs nothing.  1100 steps prepared and stepped at once (2 x 512 + 2 x 32 +
+    12) are bit-identical to 1100 steps taken 7 at a time (single launches
+    only), and prepare leaves the state and the step counter alone."""
+    w = SMALL[0]
+    _announce(f"{w.name} graph lengths")
+    lbm = _lbm()
+    a = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    before = a.populations("cur").clone()
+    a.prepare(1100)
+    a.sync()
+    assert a.t == 0 and torch.equal(a.populations("cur"), before)
+    a.step(1100)
+    b = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    for _ in range(1100 // 7):
+        b.step(7)
+    b.step(1100 % 7)
+    a.sync()
+    b.sync()
+    assert a.t == b.t == 1100
+    assert torch.equal(a.populations("cur"), b.populations("cur"))
+    assert torch.equal(a.populations("prev"), b.populations("prev"))
+    a.close()
+    b.close()
