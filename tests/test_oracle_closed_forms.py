@@ -184,3 +184,83 @@ def test_shear_wave_decays_with_common_viscosity():
     amp = float((uy * torch.sin(kw * xx)).sum() * 2 / nx)
     nu = -math.log(amp / U) / (kw * kw * steps)
     assert abs(nu / ((tau1 - 0.5) / 3) - 1) < 0.01
+
+
+# ------------------------------------------------- the same closed forms in 3-D
+def test_d3q19_binary_loschmidt_erf_along_y():
+    """The binary erf tube of the D2Q9 test on D3Q19, along y (walls at the
+    y ends, 1 x 160 x 1 nodes, periodic x and z): the D3Q19 moments recover
+    the same Fick law, so the profile follows the same erf with D_12, and
+    each species' mass is exact."""
+    D = torch.tensor([[0.0, 0.05], [0.05, 0.0]], dtype=DTYPE)
+    ny, steps = 160, 1200
+    m = evd.Model("D3Q19", 1, ny, 1, [1.0, 1.0], D, 1.0, walls=(False, True, False))
+    x0 = torch.zeros(2, 1, ny, 1, dtype=DTYPE)
+    x0[0, :, : ny // 2] = 1.0
+    x0[1, :, ny // 2:] = 1.0
+    f = evd.initial_populations(m, x0)
+    m0 = f.sum(dim=(1, 2, 3, 4))
+    f = evd.run(m, f, steps)
+    obs = evd.observables(m, f)
+    x1 = obs["x"][0, 0, :, 0].numpy()
+    ref = closed_forms.binary_erf_profile(np.arange(ny), steps, ny / 2 - 0.5, 0.05)
+    assert np.abs(x1 - ref).max() < 5e-3
+    assert ((obs["mass"] - m0).abs() / m0).max() < 1e-12
+
+
+def test_d3q19_barometric_equilibrium_along_z():
+    """Equal masses under gravity along z on D3Q19 (1 x 1 x 12, walls at the z
+    ends) relax to rho_i(z) = A_i exp(g z / c_s^2), as in 2-D."""
+    N, nz, g = 3, 12, -2e-3
+    D = torch.full((N, N), 0.1, dtype=DTYPE)
+    m = evd.Model("D3Q19", 1, 1, nz, [1.0, 1.0, 1.0], D, 1.2, g=[0, 0, g],
+                  walls=(False, False, True))
+    x0 = torch.zeros(N, nz, 1, 1, dtype=DTYPE)
+    x0[:, : nz // 2] = torch.tensor([0.2, 0.3, 0.5], dtype=DTYPE)[:, None, None, None]
+    x0[:, nz // 2:] = torch.tensor([0.6, 0.3, 0.1], dtype=DTYPE)[:, None, None, None]
+    f = evd.initial_populations(m, x0)
+    mass = f.sum(dim=(1, 2, 3, 4)).numpy()
+    f = evd.run(m, f, 3000)
+    rho = evd.observables(m, f)["rho_i"][:, :, 0, 0].numpy()
+    coords = np.stack([np.zeros(nz), np.zeros(nz), np.arange(nz)], 1)
+    ref = closed_forms.hypsometric_densities(m.M, mass, coords, [0, 0, g])
+    assert (np.abs(rho - ref) / ref).max() < 2e-5
+
+
+def test_d3q19_force_field_separates_species_by_mass_along_z():
+    """The sinusoidal force-field separation of the D2Q9 test on D3Q19, along
+    z (1 x 1 x 32, periodic): log rho_i follows phi / c_{s,i}^2."""
+    nz, A = 32, 1e-3
+    D = torch.full((2, 2), 0.15, dtype=DTYPE)
+    zz = torch.arange(nz, dtype=DTYPE)
+    ff = torch.zeros(3, nz, 1, 1, dtype=DTYPE)
+    ff[2, :, 0, 0] = A * torch.sin(2 * math.pi * zz / nz)
+    m = evd.Model("D3Q19", 1, 1, nz, [1.0, 4.0], D, 1.0, force_field=ff)
+    f = evd.initial_populations(m, torch.full((2, nz, 1, 1), 0.5, dtype=DTYPE))
+    f = evd.run(m, f, 5000)
+    rho = evd.observables(m, f)["rho_i"][:, :, 0, 0].numpy()
+    phi = -(A * nz / (2 * math.pi)) * np.cos(2 * math.pi * np.arange(nz) / nz)
+    for i, cs2 in enumerate(m.sound2()):
+        lr = np.log(rho[i]) - np.log(rho[i]).mean()
+        want = phi / cs2 - (phi / cs2).mean()
+        assert np.abs(lr - want).max() < 5e-3 * np.abs(want).max()
+
+
+def test_d3q19_shear_wave_decays_with_common_viscosity():
+    """A shear wave u_z = U sin(k x) on D3Q19 (32 x 1 x 1, masses 1:2:3) decays
+    as exp(-nu k^2 t) with nu = (tau_1 - 1/2)/3, as in 2-D."""
+    N, nx, steps, U = 3, 32, 300, 1e-3
+    tau1 = 0.8
+    D = torch.full((N, N), 0.05, dtype=DTYPE)
+    m = evd.Model("D3Q19", nx, 1, 1, [1.0, 2.0, 3.0], D, tau1)
+    xx = torch.arange(nx, dtype=DTYPE)
+    kw = 2 * math.pi / nx
+    u = torch.zeros(1, 1, nx, 3, dtype=DTYPE)
+    u[..., 2] = U * torch.sin(kw * xx)
+    rho_i = torch.full((N, 1, 1, nx), 0.3, dtype=DTYPE)
+    _, f = evd.equilibria(m, rho_i, u[None].expand(N, 1, 1, nx, 3), u)
+    f = evd.run(m, f, steps)
+    uz = evd.observables(m, f)["u"][0, 0, :, 2]
+    amp = float((uz * torch.sin(kw * xx)).sum() * 2 / nx)
+    nu = -math.log(amp / U) / (kw * kw * steps)
+    assert abs(nu / ((tau1 - 0.5) / 3) - 1) < 0.01
