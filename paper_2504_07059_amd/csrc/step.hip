@@ -19,6 +19,14 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
     const int G = gridDim.x, b = blockIdx.x;
     const int k = b & 7, idx = b >> 3, per = G >> 3, rem = G & 7;
     const int vb = k * per + (k < rem ? k : rem) + idx;
+    if (G == ntiles) {
+        // one tile per work-group (every non-persistent launch): the 64-bit
+        // divisions below are a long scalar sequence at the start of every
+        // wave, 0.1 us of a 6.2 us step on a small lattice
+        t0 = vb;
+        t1 = vb + 1;
+        return;
+    }
     t0 = (int)((int64_t)vb * ntiles / G);
     t1 = (int)((int64_t)(vb + 1) * ntiles / G);
 }
