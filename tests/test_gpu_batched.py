@@ -150,3 +150,67 @@ def test_batch_with_the_equilibrium_boundary_equals_single_runs(one_launch, pers
         assert torch.equal(sim.raw("cur", l), one.raw("cur")), (l, w.walls)
         one.close()
     sim.close()
+
+
+@pytest.mark.parametrize("one_launch", [1, 0])
+def test_batch_with_moving_walls_equals_single_runs(one_launch):
+    """Tubes with moving walls (velocities along their walls) batched with
+    tubes whose walls rest: the wall velocities are per lattice.  A batch
+    runs one kernel specialisation for all its lattices, the moving-wall one
+    here: the moving tubes are bit-identical to their runs alone, the resting
+    ones (alone they run the plain specialisation, whose multiply-adds the
+    compiler may contract differently) agree to rounding, 2e-6 of the
+    largest population as between execution variants."""
+    import dataclasses
+    base = [W.batched_tubes(count=40)[i] for i in (1, 6, 13, 27)]
+    tubes = [dataclasses.replace(w, wall_velocity=[[0.0, 0.01 * (i + 1), 0.0],
+                                                   [0.0, -0.005, 0.0]]) if i % 2 == 0 else w
+             for i, w in enumerate(base)]
+    _announce(f"moving-wall batch one_launch={one_launch}")
+    lbm = _lbm()
+    sim = _batch(tubes, block_x=64, rows=8, variant=1)
+    sim.set_batched_mode(one_launch)
+    sim.step(33)
+    sim.sync()
+    for l, w in enumerate(tubes):
+        one = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        one.set_tuning(block_x=64, rows=8, variant=1)
+        one.step(33)
+        one.sync()
+        a, b = sim.raw("cur", l), one.raw("cur")
+        if w.wall_velocity is not None:
+            assert torch.equal(a, b), (l, w.wall_velocity)
+        else:
+            assert ((a - b).abs().max() / b.abs().max()).item() < 2e-6, l
+        one.close()
+    sim.close()
+
+
+@pytest.mark.parametrize("one_launch", [1, 0])
+def test_batch_with_force_fields_equals_single_runs(one_launch):
+    """Every tube of a batch with its own force field k(x) in place of g (the
+    fields concatenated per lattice, [lattice][d][nodes]): each lattice
+    bit-identical to its run alone with its own field."""
+    import dataclasses
+    tubes = [dataclasses.replace(W.batched_tubes(count=40)[i], g=[0.0, 0.0, 0.0])
+             for i in (4, 9, 22)]
+    rng = np.random.default_rng(17)
+    fields = [(rng.uniform(-2e-6, 2e-6, size=(2, 1, w.ny, w.nx))).astype(np.float32)
+              for w in tubes]
+    _announce(f"force-field batch one_launch={one_launch}")
+    lbm = _lbm()
+    acc = torch.tensor(np.concatenate([f.reshape(-1) for f in fields]), device="cuda")
+    sim = lbm.LbmMc([lbm.params_from_workload(w) for w in tubes], W.concat_x0(tubes), accel=acc)
+    sim.set_tuning(block_x=64, rows=8, variant=1)
+    sim.set_batched_mode(one_launch)
+    sim.step(29)
+    sim.sync()
+    for l, w in enumerate(tubes):
+        one = lbm.LbmMc(lbm.params_from_workload(w), w.x0(),
+                        accel=torch.tensor(fields[l], device="cuda"))
+        one.set_tuning(block_x=64, rows=8, variant=1)
+        one.step(29)
+        one.sync()
+        assert torch.equal(sim.raw("cur", l), one.raw("cur")), l
+        one.close()
+    sim.close()
