@@ -58,6 +58,13 @@ CASES = [
         (2e-5, 0, 1e-5), 12),
     _wk("d3q19_n4_xyz_box", "D3Q19", (19, 10, 9), [1.0, 2.0, 3.0, 4.0], (True, True, True),
         (1e-5, -1e-5, 1e-5), 10),
+    # every node a corner, and walls two nodes apart
+    _wk("d2q9_n3_two_by_two_box", "D2Q9", (2, 2, 1), [1.0, 2.0, 5.0], (True, True, False),
+        (1e-5, -1e-5, 0), 20),
+    _wk("d3q19_n2_two_cube", "D3Q19", (2, 2, 2), [1.0, 3.0], (True, True, True),
+        (1e-5, 1e-5, -1e-5), 12),
+    _wk("d2q9_n2_two_columns", "D2Q9", (2, 7, 1), [1.0, 3.0], (True, False, False),
+        (2e-5, 1e-5, 0), 20),
 ]
 
 
@@ -75,7 +82,9 @@ def _oracle_run(m, f, steps):
 @pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
 def test_equilibrium_boundary_matches_oracle(w):
     """Against evd.stream_equilibrium_walls: 2-D walls on x, y and both,
-    3-D walls on z, on x and z, and on all three axes, 2-4 species."""
+    3-D walls on z, on x and z, and on all three axes, 2-4 species; and
+    boxes of 2x2 and 2x2x2 nodes (every node a corner) and a tube two nodes
+    wide."""
     _announce(f"equilibrium boundary {w.name}")
     lbm = _lbm()
     m = _model(w)
