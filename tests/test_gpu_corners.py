@@ -52,6 +52,11 @@ CASES = [
         (0, 1e-5, -1e-5), 16),
     _wk("d2q9_n3_xy_box_full", "D2Q9", (130, 37, 1), [2.0, 28.0, 44.0], (True, True, False),
         (1e-5, -2e-5, 0), 24, diff=TERNARY, forcing="full"),
+    # the smallest boxes the full corrected forcing takes (3 nodes per wall axis)
+    _wk("d2q9_n3_3x3_box_full", "D2Q9", (3, 3, 1), [1.0, 2.0, 5.0], (True, True, False),
+        (1e-5, -1e-5, 0), 24, forcing="full"),
+    _wk("d3q19_n2_3x3x3_box_full", "D3Q19", (3, 3, 3), [1.0, 4.0], (True, True, True),
+        (1e-5, 1e-5, -1e-5), 16, forcing="full"),
 ]
 
 

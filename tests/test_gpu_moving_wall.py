@@ -52,6 +52,11 @@ CASES = [
         (2e-5, 0, 0), [[0, 0.01, 0.01], [0, 0, -0.02]], 16),
     _wk("d2q9_n3_xwall_full", "D2Q9", (130, 37, 1), [2.0, 28.0, 44.0], (True, False, False),
         (1e-5, 2e-6, 0), [[0, 0.02, 0], [0, -0.01, 0]], 24, diff=TERNARY, forcing="full"),
+    # walls two nodes apart: every node next to both moving walls
+    _wk("d2q9_n2_two_columns", "D2Q9", (2, 9, 1), [1.0, 3.0], (True, False, False),
+        (1e-5, 0, 0), [[0, 0.02, 0], [0, -0.01, 0]], 24),
+    _wk("d3q19_n3_two_layers", "D3Q19", (9, 5, 2), [1.0, 2.0, 6.0], (False, False, True),
+        (0, 0, -1e-5), [[0.01, 0, 0], [0, -0.02, 0]], 16),
 ]
 
 
