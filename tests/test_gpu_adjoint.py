@@ -75,6 +75,14 @@ CASES = [
         tuning=dict(block_x=32, block_y=2, rows=4)),
     _wk("d3q19_n3_ywall", "D3Q19", (9, 10, 5), [1.0, 2.0, 6.0], (False, True, False),
         (0, 1e-5, 0), tuning=dict(block_x=32, block_y=4, rows=2, variant=0)),
+    # tiny axes: walls two nodes apart, one periodic row, one layer in 3-D
+    _wk("d2q9_n2_two_columns", "D2Q9", (2, 6, 1), [1.0, 3.0], (True, False, False),
+        (2e-5, 1e-5, 0), tuning=dict(block_x=64, rows=2)),
+    _wk("d2q9_n3_one_row", "D2Q9", (40, 1, 1), [2.0, 28.0, 44.0], (True, False, False),
+        (1e-5, 0, 0), diff=W.pairs_to_matrix(W.load_accepted()["ternary_gravity"]["pairs"], 3),
+        tuning=dict(block_x=64, rows=1)),
+    _wk("d3q19_n2_one_layer", "D3Q19", (9, 3, 1), [1.0, 4.0], (False, True, False),
+        (0, 1e-5, 0), tuning=dict(block_x=32, block_y=2, rows=1, variant=1)),
 ]
 
 
