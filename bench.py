@@ -104,14 +104,14 @@ def time_gpu(w, steps, warmup, autotune=False, tuning=None, accel=None):
 
 
 def time_variants(wh, tuning, steps=100, warmup=10):
-    """The HBM-scale workload under the optional physics of the library, at
-    the plain step's execution shape: the diffusion-driven forcing term
-    (forcing 1), the whole corrected forcing (forcing 2: a density pre-pass
-    plus gradients), a force field k(x) read at every node in place of g
-    (the same values as g, so the physics is the plain step's), and the
-    equilibrium comparison boundary in place of the Appendix A walls (a
-    plain per-node gather, one thread per column: the plain step's shape
-    when that is one, else 256-column tiles of 32 layers)."""
+    """The HBM-scale workload under the optional physics of the library, each
+    at the execution shape the autotuner picks for it (the best shape differs
+    between them): the diffusion-driven forcing term (forcing 1), the whole
+    corrected forcing (forcing 2: a density pre-pass plus gradients), a force
+    field k(x) read at every node in place of g (the same values as g, so the
+    physics is the plain step's), and the equilibrium comparison boundary in
+    place of the Appendix A walls (one thread per column: the plain step's
+    shape when that is one, else 256-column tiles of 32 layers)."""
     import dataclasses
     import torch
     res = {}
@@ -120,18 +120,20 @@ def time_variants(wh, tuning, steps=100, warmup=10):
             ("forcing_2", dataclasses.replace(wh, forcing="full"), None),
             ("force_field", dataclasses.replace(wh, g=[0.0, 0.0, 0.0]), "field"),
             ("equilibrium_boundary", dataclasses.replace(wh, wall_kind="equilibrium"), None)):
-        tun = tuning
-        if w.wall_kind == "equilibrium" and (tuning is None or tuning[4] != 0):
-            tun = (256, 1, 32, 0, 0)
+        tun = None
+        if w.wall_kind == "equilibrium":
+            tun = tuning if tuning is not None and tuning[4] == 0 else (256, 1, 32, 0, 0)
         if accel == "field":
             accel = torch.empty((2, wh.nz, wh.ny, wh.nx), dtype=torch.float32, device="cuda")
             accel[0] = wh.g[0]
             accel[1] = wh.g[1]
-        sim, out, ms, wall, drift = time_gpu(w, steps, warmup, tuning=tun, accel=accel)
+        sim, out, ms, wall, drift = time_gpu(w, steps, warmup, autotune=tun is None,
+                                             tuning=tun, accel=accel)
+        used = list(sim.get_tuning())
         sim.close()
         res[name] = {"value": wh.nodes * wh.n_species * steps / (ms * 1e3),
                      "unit": "MLUPS x species", "ms_per_step": ms / steps, "steps": steps,
-                     "mass_drift": drift}
+                     "mass_drift": drift, "tuning": used}
         del accel
     return res
 

@@ -380,8 +380,9 @@ struct Tuning {
 constexpr int kGraphSteps[2] = {512, 32};
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, Tuning> g_tune_cache;
-// (the cache key: lattice, species, nx, ny, nz of the first lattice, lattice count)
+std::map<std::tuple<int, int, int, int, int, int, int>, Tuning> g_tune_cache;
+// (the cache key: lattice, species, nx, ny, nz of the first lattice, lattice count,
+// and the kernel specialisation: forcing, force field, moving walls)
 
 }  // namespace
 
@@ -436,6 +437,15 @@ struct lbm_mc_ctx {
 };
 
 namespace {
+
+// The kernel specialisation a context's steps run (the best shape differs:
+// the full corrected forcing favours the species-split variant on shapes
+// where the plain step does not).
+int tune_kind(const lbm_mc_ctx* c) {
+    int moving = 0;
+    for (const auto& h : c->hlp) moving |= h.moving;
+    return c->params[0].forcing + 3 * (c->accel ? 1 : 0) + 6 * moving;
+}
 
 void drop_graphs(lbm_mc_ctx* c) {
     for (auto& row : c->gexec)
@@ -914,7 +924,8 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
         t.split = 0;   // the equilibrium boundary runs one thread per column
     } else {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find({c->lattice, c->N, p[0].nx, p[0].ny, p[0].nz, n_lattices});
+        auto it = g_tune_cache.find(
+            {c->lattice, c->N, p[0].nx, p[0].ny, p[0].nz, n_lattices, tune_kind(c)});
         if (it != g_tune_cache.end()) t = it->second;
     }
     c->tune = t;
@@ -1171,7 +1182,7 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     if (!c->hlp[0].eqb) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const auto& q = c->params[0];
-        g_tune_cache[{c->lattice, c->N, q.nx, q.ny, q.nz, c->L}] = bestt;
+        g_tune_cache[{c->lattice, c->N, q.nx, q.ny, q.nz, c->L, tune_kind(c)}] = bestt;
     }
     // the candidates wrote f~ into prev: it no longer holds f~(t-1)
     c->prev_valid = false;
