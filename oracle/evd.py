@@ -43,6 +43,9 @@ Readings taken where the paper is silent (each repeated at its function):
      of what its populations would stream beyond the walls, split by the set
      of walls crossed (see _wall_returns); it reduces to Appendix A for one
      wall, to halfway bounce-back at c = 1, and conserves mass;
+  R12 the real species velocity of a species with rho_i = 0 at a node (eq.
+     CE_EQ83 divides Theta_i by rho_i) is the limit rho_i -> 0, in which
+     Theta_i/rho_i = sum_j rho_j/(rho tau_ij)(u_i^eq - u_j^eq);
   R10 the moving-wall term of Appendix A takes rho_i and the mass fraction
      w_i of the streamed populations at the wall node (the term adds no mass,
      so they do not depend on it), and a wall moves only along itself.
@@ -299,6 +302,20 @@ def theta(model, rho_i, rho, ueq, Y):
             if i != j:
                 out[i] = out[i] + (rho_i[i] * rho_i[j] / rho * Y[i, j])[..., None] \
                     * (ueq[i] - ueq[j])
+    return out
+
+
+def theta_per_density(model, rho_i, rho, ueq, Y):
+    """Theta_i / rho_i = sum_j (rho_j / (rho tau_ij)) (u_i^eq - u_j^eq), from
+    eq. (CE_theta_definition) with the common factor rho_i cancelled; where
+    rho_i = 0 this is the limit of Theta_i/rho_i (reading R12).
+    [N, nz, ny, nx, 3]."""
+    N = model.N
+    out = torch.zeros_like(ueq)
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                out[i] = out[i] + (rho_i[j] / rho * Y[i, j])[..., None] * (ueq[i] - ueq[j])
     return out
 
 
@@ -665,15 +682,16 @@ def observables(model, f):
       Theta_i = sum_j rho_i rho_j/(rho tau_ij) (u_i^eq - u_j^eq)
                                                    (eq. CE_theta_definition)
       u_i = u_i^eq - dt Theta_i/(2 rho_i)            (eq. CE_EQ83)
-    plus rho_i, u_i^eq, rho, u, n, p and the FP64 total mass of each species."""
+    (Theta_i/rho_i by theta_per_density, so a species with rho_i = 0 takes the
+    limit, reading R12), plus rho_i, u_i^eq, rho, u, n, p and the FP64 total
+    mass of each species."""
     rho_i, ueq = species_moments(model, f)
     rho, u, n, p = mixture(model, rho_i, ueq)
     Y = cross_relaxation(model, rho_i, rho, n, p)
     M = torch.tensor(model.M, dtype=DTYPE)
     x = rho_i / (M[:, None, None, None] * n)
     th = theta(model, rho_i, rho, ueq, Y)
-    safe = torch.where(rho_i == 0, torch.ones_like(rho_i), rho_i)
-    u_real = ueq - 0.5 * th / safe[..., None]
+    u_real = ueq - 0.5 * theta_per_density(model, rho_i, rho, ueq, Y)
     return {
         "rho_i": rho_i, "ueq": ueq, "rho": rho, "u": u, "n": n, "p": p,
         "x": x, "tau_inv": Y, "theta": th, "u_i": u_real,
