@@ -231,15 +231,25 @@ lbm_mc_status lbm_mc_sync(lbm_mc_ctx* ctx);
  *   rho   device float [lattice][N][nz][ny][nx]: species densities rho_i.
  *   x     device float, same layout: mole fractions x_i = rho_i/(M_i n).
  *   u     device float [lattice][d][nz][ny][nx]: mixture velocity
- *         u = sum_i w_i u_i^eq with the force-shifted u_i^eq (d = 2 or 3).
+ *         u = sum_i w_i u_i^eq with the force-shifted u_i^eq (d = 2 or 3;
+ *         eq. Sirovich_mixture_velocity).
+ *   ueq   device float [lattice][N][d][nz][ny][nx]: the force-shifted
+ *         equilibrium velocity u_i^eq of every species (eq.
+ *         first_order_moment_force; a species with rho_i = 0 at a node takes
+ *         g/2 there).
+ *   us    device float, same layout: the real species velocity
+ *         u_i = u_i^eq - Theta_i/(2 rho_i) (eq. CE_EQ83, dt = 1), Theta_i of
+ *         eq. (CE_theta_definition) with the cross-relaxation times of the
+ *         step; Theta_i/rho_i = sum_j rho_j/(rho tau_ij)(u_i^eq - u_j^eq), which
+ *         is also its value where rho_i = 0.
  *   mass      host double [lattice][N]: total mass of each species (FP64 sum).
  *   momentum  host double [lattice][d]: total sum_x rho u (FP64 sum).
- * Node-field offsets of each lattice: lbm_mc_layout field_offsets (times N or d).
- * Requesting mass or momentum synchronises the stream.  Errors:
+ * Node-field offsets of each lattice: lbm_mc_layout field_offsets (times N,
+ * d or N*d).  Requesting mass or momentum synchronises the stream.  Errors:
  * LBM_MC_ERR_INVALID, LBM_MC_ERR_HIP, LBM_MC_ERR_NONFINITE (as lbm_mc_sync).
  */
-lbm_mc_status lbm_mc_moments(lbm_mc_ctx* ctx, float* rho, float* x, float* u,
-                             double* mass, double* momentum);
+lbm_mc_status lbm_mc_moments(lbm_mc_ctx* ctx, float* rho, float* x, float* u, float* ueq,
+                             float* us, double* mass, double* momentum);
 
 /* Current buffers and step: *cur holds f~(t), *prev holds f~(t-1) (f(0) at t = 0).
  * Any out pointer may be NULL. */
@@ -284,6 +294,35 @@ lbm_mc_status lbm_mc_adjoint_step(lbm_mc_ctx* ctx, const float* f_prev, const fl
  * to lbm_mc_init (the context keeps a device copy).
  */
 lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* ctx, const float* lam0, double* grad);
+
+/*
+ * Mole-fraction profile along x of a stored state (single-lattice contexts):
+ *     xbar_i(x) = (1/(ny nz)) sum over y, z of x_i(x, y, z),
+ * x_i = rho_i/(M_i n), n = sum_j rho_j/M_j (Sec. 3), rho_i = P0/w_0 + sum g_a
+ * of the state (the collision conserves rho_i, so this is the profile of the
+ * observables at that step; Sec. 4.1 reports such region averages).
+ * Evaluated in FP64 with a fixed-order reduction (reproducible).
+ *   state  device float, population layout (buffer_floats), e.g. a buffer of
+ *          lbm_mc_state or a checkpoint; read only.
+ *   xbar   device double [N][nx], written.
+ * Uses a context-owned scratch array of FP64 partial sums (allocated on first
+ * use, a few MB at most).  Errors: LBM_MC_ERR_INVALID (NULL pointers),
+ * LBM_MC_ERR_UNSUPPORTED (batched context), LBM_MC_ERR_HIP.
+ */
+lbm_mc_status lbm_mc_profile(lbm_mc_ctx* ctx, const float* state, double* xbar);
+
+/*
+ * Vector-Jacobian product of lbm_mc_profile at `state`: given
+ * dxbar = dL/dxbar (device double [N][nx]), writes lam = dL/dstate (device
+ * float, population layout) at every node: with d_i = dxbar_i(x),
+ *   dL/drho_j = (d_j - sum_i d_i x_i) / (ny nz M_j n),
+ *   lam(P0_j) = dL/drho_j / w_0,   lam(g_{j,a}) = dL/drho_j   (a >= 1).
+ * This is the adjoint lam(T) that starts the reverse sweep of a loss of the
+ * final profile.  The row padding of lam is not touched; lam must not alias
+ * state.  Errors as lbm_mc_profile.
+ */
+lbm_mc_status lbm_mc_profile_vjp(lbm_mc_ctx* ctx, const float* state, const double* dxbar,
+                                 float* lam);
 
 /*
  * Recompute n steps from the state src into a state sequence: slot k of

@@ -46,13 +46,15 @@ def _load():
         "lbm_mc_step": [vp, c_int64],
         "lbm_mc_prepare": [vp, c_int64],
         "lbm_mc_sync": [vp],
-        "lbm_mc_moments": [vp, vp, vp, vp, P(c_double), P(c_double)],
+        "lbm_mc_moments": [vp, vp, vp, vp, vp, vp, P(c_double), P(c_double)],
         "lbm_mc_state": [vp, P(vp), P(vp), P(c_int64)],
         "lbm_mc_restore": [vp, vp, vp, c_int64],
         "lbm_mc_adjoint_step": [vp, vp, vp, vp, vp],
         "lbm_mc_adjoint_init": [vp, vp, vp],
         "lbm_mc_replay": [vp, vp, c_int64, vp, c_int64],
         "lbm_mc_adjoint_run": [vp, vp, c_int64, c_int64, vp, vp, vp],
+        "lbm_mc_profile": [vp, vp, vp],
+        "lbm_mc_profile_vjp": [vp, vp, vp, vp],
         "lbm_mc_set_tuning": [vp, c_int32, c_int32, c_int32, c_int32, c_int32],
         "lbm_mc_get_tuning": [vp, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32)],
         "lbm_mc_autotune": [vp, c_int32, P(c_double)],

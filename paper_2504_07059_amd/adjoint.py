@@ -5,8 +5,10 @@ checkpoints every K steps and recomputation of each segment.
 
 The differentiable inputs are the pair diffusivities D_ij (i < j, row-major)
 and the specific body force g (F_i = rho_i g, eq. MS_equation); the output is
-the stored state s(T) after T steps, from which a loss is built with torch
-operations (``mole_fractions`` gives x_i = rho_i/(M_i n), Sec. 3).  Every
+the mole-fraction profile xbar_i(x) after T steps (the mean over y and z of
+x_i = rho_i/(M_i n), Sec. 3), computed by the library, whose backward starts
+from the library's vector-Jacobian product of that profile.  A loss is any
+torch function of the profile (``profile_misfit`` is the L2 misfit).  Every
 step of the forward and reverse sweeps runs in the library's kernels; the
 parameter gradients are accumulated in FP64 on the device.
 """
@@ -17,9 +19,6 @@ import numpy as np
 import torch
 
 from . import lbm
-
-WEIGHTS = lbm.LATTICE_WEIGHTS
-
 
 @dataclass
 class Problem:
@@ -71,7 +70,8 @@ def _sim(problem, pairs, g):
 
 
 class Evolve(torch.autograd.Function):
-    """s(T) = Phi^T(s(0; D, g); D, g) with s(0) the initialised state."""
+    """xbar(T): the profile of s(T) = Phi^T(s(0; D, g); D, g), s(0) the
+    initialised state."""
 
     @staticmethod
     def forward(ctx, pairs, g, problem):
@@ -88,19 +88,20 @@ class Evolve(torch.autograd.Function):
             n = min(K, problem.steps - t)
             sim.step(n)
             t += n
-        out = sim.raw("cur").clone()
-        ctx.sim, ctx.ckpts, ctx.problem = sim, ckpts, problem
+        s_T = sim.buffers()[0].clone()
+        xbar = sim.profile(s_T)
+        ctx.sim, ctx.ckpts, ctx.problem, ctx.s_T = sim, ckpts, problem, s_T
         ctx.pairs_meta = (pairs.device, pairs.dtype)
         ctx.g_meta = (g.device, g.dtype)
-        return out
+        return xbar
 
     @staticmethod
-    def backward(ctx, lam_T):
+    def backward(ctx, dxbar):
         sim, problem = ctx.sim, ctx.problem
         dev = sim.device
         lam_a = torch.zeros(sim.total, dtype=torch.float32, device=dev)
         lam_b = torch.zeros_like(lam_a)
-        sim.view(lam_a).copy_(lam_T.to(torch.float32))
+        sim.profile_vjp(ctx.s_T, dxbar, lam_a)
         grad = torch.zeros(problem.n_pairs + 3, dtype=torch.float64, device=dev)
         K = int(problem.checkpoint_every)
         stride = (sim.total + 63) // 64 * 64
@@ -115,36 +116,18 @@ class Evolve(torch.autograd.Function):
         sim.adjoint_init(lam_a, grad)
         ctx.sim = None
         ctx.ckpts = None
+        ctx.s_T = None
         npair = problem.n_pairs
         return (grad[:npair].to(*ctx.pairs_meta), grad[npair:].to(*ctx.g_meta), None)
 
 
 def evolve(pairs, g, problem):
-    """Differentiable run: returns the stored state s(T) [N, Q, nz, ny, nx]
-    (float32, on the device) for parameters pairs [n_pairs] and g [3]."""
+    """Differentiable run: returns the mole-fraction profile xbar [N, nx]
+    (float64, on the device) after problem.steps steps, for parameters
+    pairs [n_pairs] and g [3]."""
     return Evolve.apply(pairs, g, problem)
 
 
-def densities(state, Q):
-    """Species densities rho_i = P0/w_0 + sum_{a>=1} g_a of a stored state
-    [N, Q, ...], in float64 (the collision conserves rho_i, so these are also
-    the densities of the streamed populations)."""
-    s = state.double()
-    return s[:, 0] / WEIGHTS[Q][0] + s[:, 1:].sum(dim=1)
-
-
-def mole_fractions(state, masses, Q):
-    """x_i = rho_i/(M_i n), n = sum_j rho_j/M_j (Sec. 3), of a stored state."""
-    rho = densities(state, Q)
-    M = torch.tensor([m / masses[0] for m in masses], dtype=torch.float64,
-                     device=rho.device).view(-1, *([1] * (rho.dim() - 1)))
-    nm = rho / M
-    return nm / nm.sum(dim=0, keepdim=True)
-
-
-def profile_misfit(state, masses, Q, target):
-    """sum_s sum_x (xbar_s(x) - target_s(x))^2 with xbar the mean of the mole
-    fraction over y and z: target [N, nx]."""
-    x = mole_fractions(state, masses, Q)              # [N, nz, ny, nx]
-    xbar = x.mean(dim=(1, 2))
+def profile_misfit(xbar, target):
+    """sum_s sum_x (xbar_s(x) - target_s(x))^2, target [N, nx]."""
     return ((xbar - target) ** 2).sum()

@@ -80,7 +80,7 @@ hipError_t launch_init(int lattice, int nspecies, const LatParams* lp_dev, int l
                        const LatParams& lp_host, const double* x0_dev, const float* accel,
                        float* f0_out, float* ft_out, unsigned* flag, hipStream_t s);
 hipError_t launch_moments(int lattice, int nspecies, const Launch& L, int direct, float* rho,
-                          float* x, float* u, double* partial, int nq);
+                          float* x, float* u, float* ueq, float* us, double* partial, int nq);
 hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
                          double* totals, hipStream_t s);
 // adjoint: kernel A (collision VJP into mu, gradient partials per tile),
@@ -93,6 +93,14 @@ hipError_t launch_adjoint_stream(int lattice, int nspecies, const Launch& L, con
 hipError_t launch_adjoint_init(int lattice, int nspecies, const LatParams* lp_dev,
                                const LatParams& lp_host, const double* x0, const float* lam0,
                                double* gpart, int nblocks, hipStream_t s);
+// mole-fraction profile along x of a stored state (partials per row chunk,
+// then a fixed-order sum) and its vector-Jacobian product (single lattice)
+hipError_t launch_profile(int lattice, int nspecies, const LatParams* lp_dev,
+                          const LatParams& lp_host, const float* state, int rows_per,
+                          int nchunks, double* part, double* xbar, hipStream_t s);
+hipError_t launch_profile_vjp(int lattice, int nspecies, const LatParams* lp_dev,
+                              const LatParams& lp_host, const float* state, const double* dxbar,
+                              float* lam, int max_blocks, hipStream_t s);
 hipError_t launch_grad_reduce(const LatParams* lp_dev, const double* gpart, int nblocks, int ng,
                               int nspecies, double* grad, hipStream_t s);
 

@@ -434,6 +434,9 @@ struct lbm_mc_ctx {
     double* dgpart = nullptr;
     size_t dgpart_cap = 0;
     double* dx0 = nullptr;
+    // profile partial sums [chunks][N][nx] (allocated on first use)
+    double* dprof = nullptr;
+    size_t dprof_cap = 0;
 };
 
 namespace {
@@ -721,6 +724,25 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
         HIPCHECK(hipMalloc(&c->dgpart, need * sizeof(double)));
         c->dgpart_cap = need;
     }
+    return LBM_MC_OK;
+}
+
+// Row chunks of the profile reduction: enough work-groups to fill the chip
+// (about 2048 of 64 columns), each chunk at least one row.
+void profile_chunks(const lbm_mc_ctx* c, int& rows_per, int& nchunks) {
+    const auto& q = c->params[0];
+    const int64_t rows = (int64_t)q.ny * q.nz;
+    const int64_t xb = (q.nx + 63) / 64;
+    int64_t want = std::max<int64_t>(1, std::min<int64_t>(rows, (2048 + xb - 1) / xb));
+    rows_per = (int)((rows + want - 1) / want);
+    nchunks = (int)((rows + rows_per - 1) / rows_per);
+}
+
+lbm_mc_status profile_check(lbm_mc_ctx* c, const float* state, const void* out) {
+    if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
+    if (c->L != 1)
+        return fail(LBM_MC_ERR_UNSUPPORTED, "profile: batched contexts are not supported");
+    if (!state || !out) return fail(LBM_MC_ERR_INVALID, "profile: NULL buffer");
     return LBM_MC_OK;
 }
 
@@ -1016,15 +1038,16 @@ lbm_mc_status lbm_mc_sync(lbm_mc_ctx* c) {
     return check_flag(c);
 }
 
-lbm_mc_status lbm_mc_moments(lbm_mc_ctx* c, float* rho, float* x, float* u, double* mass,
-                             double* momentum) {
+lbm_mc_status lbm_mc_moments(lbm_mc_ctx* c, float* rho, float* x, float* u, float* ueq,
+                             float* us, double* mass, double* momentum) {
     if (!c) return fail(LBM_MC_ERR_INVALID, "ctx is NULL");
     if (!c->prev_valid)
         return fail(LBM_MC_ERR_INVALID, "moments need f~(t-1): restore it or take one step");
     const int nq = c->N + 3;
     Launch L = make_launch(c, c->prev, nullptr, c->stream);
     if (c->tune.bx * c->tune.by % 64) return fail(LBM_MC_ERR_INVALID, "block size must be a multiple of 64");
-    HIPCHECK(launch_moments(c->lattice, c->N, L, c->t == 0 ? 1 : 0, rho, x, u, c->dpartial, nq));
+    HIPCHECK(launch_moments(c->lattice, c->N, L, c->t == 0 ? 1 : 0, rho, x, u, ueq, us,
+                            c->dpartial, nq));
     if (mass || momentum) {
         HIPCHECK(launch_reduce(c->dlp, c->L, c->dpartial, nq, c->dtotals, c->stream));
         std::vector<double> h((size_t)c->L * nq);
@@ -1213,6 +1236,7 @@ lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
     hipFree(c->dlam);
     hipFree(c->dx0);
     hipFree(c->adj_tiles);
+    hipFree(c->dprof);
     delete c;
     return LBM_MC_OK;
 }
@@ -1242,6 +1266,36 @@ lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* c, const float* lam0, double* grad
     HIPCHECK(launch_adjoint_init(c->lattice, c->N, c->dlp, c->hlp[0], c->dx0, lam0, c->dgpart, nb,
                                  c->stream));
     return grad_sum(c, nb, grad);
+}
+
+lbm_mc_status lbm_mc_profile(lbm_mc_ctx* c, const float* state, double* xbar) {
+    lbm_mc_status st = profile_check(c, state, xbar);
+    if (st != LBM_MC_OK) return st;
+    int rows_per, nchunks;
+    profile_chunks(c, rows_per, nchunks);
+    const size_t need = (size_t)nchunks * c->N * c->params[0].nx;
+    if (need > c->dprof_cap) {
+        if (c->dprof) hipFree(c->dprof);
+        c->dprof = nullptr;
+        c->dprof_cap = 0;
+        HIPCHECK(hipMalloc(&c->dprof, need * sizeof(double)));
+        c->dprof_cap = need;
+    }
+    HIPCHECK(launch_profile(c->lattice, c->N, c->dlp, c->hlp[0], state, rows_per, nchunks,
+                            c->dprof, xbar, c->stream));
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_profile_vjp(lbm_mc_ctx* c, const float* state, const double* dxbar,
+                                 float* lam) {
+    lbm_mc_status st = profile_check(c, state, lam);
+    if (st != LBM_MC_OK) return st;
+    if (!dxbar) return fail(LBM_MC_ERR_INVALID, "profile_vjp: NULL buffer");
+    if ((const void*)lam == (const void*)state)
+        return fail(LBM_MC_ERR_INVALID, "profile_vjp: lam must not alias state");
+    HIPCHECK(launch_profile_vjp(c->lattice, c->N, c->dlp, c->hlp[0], state, dxbar, lam,
+                                c->cus * 8, c->stream));
+    return LBM_MC_OK;
 }
 
 lbm_mc_status lbm_mc_replay(lbm_mc_ctx* c, const float* src, int64_t n, float* states,

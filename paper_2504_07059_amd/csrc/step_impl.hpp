@@ -1,5 +1,9 @@
 // Forward kernels: the fused time step, the initial state, and the
-// observables with their FP64 reductions.
+// observables with their FP64 reductions, with launchers templated on the
+// lattice.  Each lattice is compiled in its own translation unit
+// (step_d2q9.hip, step_d3q19.hip); step.hip dispatches between them.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -441,6 +445,8 @@ struct MomOp {
     float* rho_out;
     float* x_out;
     float* u_out;
+    float* ueq_out;          // [N][d][nodes]: u_i^eq
+    float* us_out;           // [N][d][nodes]: u_i = u_i^eq - Theta_i/(2 rho_i)
     int64_t nodes;
     int nx, ny, x, y;
     CollConst C;
@@ -484,6 +490,28 @@ struct MomOp {
             if (u_out) u_out[d * nodes + node] = U[d] * iR;
             acc[NS + d] += (double)U[d];   // rho u = sum_i rho_i u_i^eq
         }
+        if (ueq_out) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ueq_out[(s * DIM + d) * nodes + node] = ue[s][d];
+        }
+        if (us_out) {
+            // eq. (CE_EQ83) with Theta_i of eq. (CE_theta_definition):
+            // Theta_i/rho_i = sum_j rho_j/(rho tau_ij) (u_i^eq - u_j^eq), the
+            // friction vector V_i of the collision (its limit where rho_i = 0)
+            const Mix Mx = mixture<NS>(rho, ue, C);
+            float y[NS][NS];
+            tau_solve<NS>(rho, Mx.R, Mx.n, C, y);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                float V[3];
+                friction<NS>(s, rho, ue, y, Mx.iR, V);
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+                    us_out[(s * DIM + d) * nodes + node] = fmaf(-0.5f, V[d], ue[s][d]);
+            }
+        }
     }
 };
 
@@ -492,8 +520,9 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
                                                  const LatParams* __restrict__ lps,
                                                  const Tile* __restrict__ tiles, int direct,
                                                  const float* __restrict__ accel,
-                                                 float* rho, float* xo, float* u,
-                                                 double* __restrict__ partial, int nq) {
+                                                 float* rho, float* xo, float* u, float* ueq,
+                                                 float* us, double* __restrict__ partial,
+                                                 int nq) {
     constexpr int Q = Lat<LAT>::Q;
     constexpr int DIM = Lat<LAT>::DIM;
     __shared__ double red[4][NS + 3];
@@ -507,6 +536,8 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
     op.rho_out = rho ? rho + P.field_base * NS : nullptr;
     op.x_out = xo ? xo + P.field_base * NS : nullptr;
     op.u_out = u ? u + P.field_base * DIM : nullptr;
+    op.ueq_out = ueq ? ueq + P.field_base * NS * DIM : nullptr;
+    op.us_out = us ? us + P.field_base * NS * DIM : nullptr;
     op.nodes = nodes;
     op.nx = P.nx; op.ny = P.ny; op.x = x; op.y = y;
     op.C = coll_const(P);
@@ -555,62 +586,37 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
     }
 }
 
-// Fixed-order FP64 sum of the per-tile partials of each lattice: one
-// work-group per lattice, thread t takes tiles begin+t, begin+t+256, ..., then
-// a fixed shuffle and LDS tree (reproducible run to run).
-__global__ void __launch_bounds__(256) k_reduce(const LatParams* __restrict__ lps, int nlat,
-                                                const double* __restrict__ partial, int nq,
-                                                double* __restrict__ totals) {
-    __shared__ double red[4];
-    const int l = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int t0 = lps[l].tile_begin, t1 = lps[l].tile_end;
-    for (int q = 0; q < nq; ++q) {
-        double v = 0.0;
-        for (int t = t0 + tid; t < t1; t += 256) v += partial[(int64_t)t * nq + q];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) red[wave] = v;
-        __syncthreads();
-        if (tid == 0) totals[(int64_t)l * nq + q] = (red[0] + red[1]) + (red[2] + red[3]);
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- launchers
 // Calls fn(lattice, species count, forcing, extension) with the four as
 // compile-time constants; extension 0: constant g and resting walls, 1: a
 // force field, 2: moving walls, 3: the equilibrium comparison boundary.
-template <typename Fn>
-static hipError_t by_shape(int lattice, int ns, int frc, int ext, Fn&& fn) {
+template <int LAT, typename Fn>
+static hipError_t by_shape(int ns, int frc, int ext, Fn&& fn) {
     using std::integral_constant;
-    auto with_ext = [&](auto lat, auto n, auto f) -> hipError_t {
+    constexpr integral_constant<int, LAT> lat{};
+    auto with_ext = [&](auto n, auto f) -> hipError_t {
         if (ext == 0) return fn(lat, n, f, integral_constant<int, 0>{});
         if (ext == 1) return fn(lat, n, f, integral_constant<int, 1>{});
         if (ext == 2) return fn(lat, n, f, integral_constant<int, 2>{});
         if (ext == 3) return fn(lat, n, f, integral_constant<int, 3>{});
         return hipErrorInvalidValue;
     };
-    auto with_frc = [&](auto lat, auto n) -> hipError_t {
-        if (frc == 0) return with_ext(lat, n, integral_constant<int, 0>{});
-        if (frc == 1) return with_ext(lat, n, integral_constant<int, 1>{});
-        if (frc == 2) return with_ext(lat, n, integral_constant<int, 2>{});
+    auto with_frc = [&](auto n) -> hipError_t {
+        if (frc == 0) return with_ext(n, integral_constant<int, 0>{});
+        if (frc == 1) return with_ext(n, integral_constant<int, 1>{});
+        if (frc == 2) return with_ext(n, integral_constant<int, 2>{});
         return hipErrorInvalidValue;
     };
-    auto with_ns = [&](auto lat) -> hipError_t {
-        if (ns == 2) return with_frc(lat, integral_constant<int, 2>{});
-        if (ns == 3) return with_frc(lat, integral_constant<int, 3>{});
-        if (ns == 4) return with_frc(lat, integral_constant<int, 4>{});
-        return hipErrorInvalidValue;
-    };
-    if (lattice == 0) return with_ns(integral_constant<int, 0>{});
-    if (lattice == 1) return with_ns(integral_constant<int, 1>{});
+    if (ns == 2) return with_frc(integral_constant<int, 2>{});
+    if (ns == 3) return with_frc(integral_constant<int, 3>{});
+    if (ns == 4) return with_frc(integral_constant<int, 4>{});
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(int lattice, int ns, const Launch& L) {
+template <int LAT_>
+hipError_t launch_step_lat(int ns, const Launch& L) {
     if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
-    return by_shape(lattice, ns, L.forcing, L.eqb ? 3 : (L.accel ? 1 : (L.moving ? 2 : 0)),
+    return by_shape<LAT_>(ns, L.forcing, L.eqb ? 3 : (L.accel ? 1 : (L.moving ? 2 : 0)),
                     [&](auto lat, auto n, auto frc, auto ex) -> hipError_t {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value, EXT = decltype(ex)::value;
@@ -659,13 +665,14 @@ hipError_t launch_step(int lattice, int ns, const Launch& L) {
     });
 }
 
-hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const LatParams& h,
-                       const double* x0, const float* accel, float* f0, float* ft,
-                       unsigned* flag, hipStream_t s) {
+template <int LAT_>
+hipError_t launch_init_lat(int ns, const LatParams* lp, int lat, const LatParams& h,
+                           const double* x0, const float* accel, float* f0, float* ft,
+                           unsigned* flag, hipStream_t s) {
     const int64_t nodes = (int64_t)h.nx * h.ny * h.nz;
     const int64_t blocks = std::min<int64_t>((nodes + 255) / 256, 65536);
     // the initial collision acts on f(0), which has not been streamed: no wall terms
-    return by_shape(lattice, ns, h.forcing, accel ? 1 : 0,
+    return by_shape<LAT_>(ns, h.forcing, accel ? 1 : 0,
                     [&](auto la, auto n, auto frc, auto ex) {
         constexpr int LAT = decltype(la)::value, NS = decltype(n)::value,
                       FRC = decltype(frc)::value, EXT = decltype(ex)::value;
@@ -681,36 +688,25 @@ hipError_t launch_init(int lattice, int ns, const LatParams* lp, int lat, const 
 
 template <int LAT, int NS>
 static hipError_t launch_moments_t(const Launch& L, int direct, float* rho, float* x, float* u,
-                                   double* partial, int nq) {
+                                   float* ueq, float* us, double* partial, int nq) {
     if (L.eqb)
         hipLaunchKernelGGL((k_moments<LAT, NS, true>), dim3(L.ntiles), dim3(L.bx, L.by), 0,
-                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, partial,
-                           nq);
+                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, ueq, us,
+                           partial, nq);
     else
         hipLaunchKernelGGL((k_moments<LAT, NS, false>), dim3(L.ntiles), dim3(L.bx, L.by), 0,
-                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, partial,
-                           nq);
+                           L.stream, L.src, L.lp, L.tiles, direct, L.accel, rho, x, u, ueq, us,
+                           partial, nq);
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int lattice, int ns, const Launch& L, int direct, float* rho, float* x,
-                          float* u, double* partial, int nq) {
-    if (lattice == 0) {
-        if (ns == 2) return launch_moments_t<0, 2>(L, direct, rho, x, u, partial, nq);
-        if (ns == 3) return launch_moments_t<0, 3>(L, direct, rho, x, u, partial, nq);
-        if (ns == 4) return launch_moments_t<0, 4>(L, direct, rho, x, u, partial, nq);
-    } else {
-        if (ns == 2) return launch_moments_t<1, 2>(L, direct, rho, x, u, partial, nq);
-        if (ns == 3) return launch_moments_t<1, 3>(L, direct, rho, x, u, partial, nq);
-        if (ns == 4) return launch_moments_t<1, 4>(L, direct, rho, x, u, partial, nq);
-    }
+template <int LAT>
+hipError_t launch_moments_lat(int ns, const Launch& L, int direct, float* rho, float* x,
+                              float* u, float* ueq, float* us, double* partial, int nq) {
+    if (ns == 2) return launch_moments_t<LAT, 2>(L, direct, rho, x, u, ueq, us, partial, nq);
+    if (ns == 3) return launch_moments_t<LAT, 3>(L, direct, rho, x, u, ueq, us, partial, nq);
+    if (ns == 4) return launch_moments_t<LAT, 4>(L, direct, rho, x, u, ueq, us, partial, nq);
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_reduce(const LatParams* lp, int nlat, const double* partial, int nq,
-                         double* totals, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(nlat), dim3(256), 0, s, lp, nlat, partial, nq, totals);
-    return hipGetLastError();
 }
 
 }  // namespace lbmmc

@@ -10,10 +10,6 @@ from . import _lib
 from ._lib import Params, check, lib
 
 
-LATTICE_WEIGHTS = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
-                   19: [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12}
-
-
 def make_params(lattice, nx, ny, nz, masses, diff, tau1, g=(0.0, 0.0, 0.0),
                 walls=(False, False, False), n0=0.0, forcing=0, wall_velocity=None,
                 wall_kind="appendix_a"):
@@ -159,44 +155,42 @@ class LbmMc:
         v = buf[self.offsets[lattice]: self.offsets[lattice] + n]
         return v.view(self.N, self.Q, p.nz, p.ny, self.pitch[lattice])[..., : p.nx]
 
-    def populations(self, which="cur", lattice=0):
-        """Post-collision populations f~ [N, Q, nz, ny, nx] of one lattice, in
-        float64, rebuilt from the stored state: f~_0 = P0 and
-        f~_a = (w_a/w_0) P0 + g_a for a >= 1."""
-        r = self.raw(which, lattice).double()
-        w = torch.tensor(LATTICE_WEIGHTS[self.Q], dtype=torch.float64, device=r.device)
-        p0 = r[:, :1]
-        f = (w / w[0])[None, :, None, None, None] * p0 + r
-        f[:, 0] = p0[:, 0]
-        return f
-
-    def moments(self, fields=True):
+    def moments(self, fields=True, velocities=False):
         """Observables of f(t): dict with 'rho', 'x' [sum_l N*nodes], 'u'
-        [sum_l dim*nodes] (device tensors) and 'mass' [L, N], 'momentum' [L, dim]
-        (numpy float64)."""
+        [sum_l dim*nodes] (device tensors), with velocities also 'ueq' and
+        'us' [sum_l N*dim*nodes] (u_i^eq and the real species velocity u_i),
+        and 'mass' [L, N], 'momentum' [L, dim] (numpy float64)."""
         tot = sum(self.nodes)
         out = {}
+        f32 = dict(dtype=torch.float32, device=self.device)
         if fields:
-            out["rho"] = torch.empty(tot * self.N, dtype=torch.float32, device=self.device)
-            out["x"] = torch.empty(tot * self.N, dtype=torch.float32, device=self.device)
-            out["u"] = torch.empty(tot * self.dim, dtype=torch.float32, device=self.device)
+            out["rho"] = torch.empty(tot * self.N, **f32)
+            out["x"] = torch.empty(tot * self.N, **f32)
+            out["u"] = torch.empty(tot * self.dim, **f32)
+        if velocities:
+            out["ueq"] = torch.empty(tot * self.N * self.dim, **f32)
+            out["us"] = torch.empty(tot * self.N * self.dim, **f32)
         mass = np.zeros((self.L, self.N))
         mom = np.zeros((self.L, self.dim))
         dp = ctypes.POINTER(ctypes.c_double)
         check(lib.lbm_mc_moments(self.ctx, _ptr(out.get("rho")), _ptr(out.get("x")),
-                                 _ptr(out.get("u")), mass.ctypes.data_as(dp),
-                                 mom.ctypes.data_as(dp)))
+                                 _ptr(out.get("u")), _ptr(out.get("ueq")), _ptr(out.get("us")),
+                                 mass.ctypes.data_as(dp), mom.ctypes.data_as(dp)))
         out["mass"] = mass
         out["momentum"] = mom
         return out
 
     def field(self, out, name, lattice=0):
-        """Reshape a node field of `moments()` for one lattice: [k, nz, ny, nx]."""
+        """Reshape a node field of `moments()` for one lattice: [k, nz, ny, nx]
+        ('rho', 'x': k = N; 'u': k = dim), or [N, dim, nz, ny, nx] ('ueq', 'us')."""
         p = self.params[lattice]
-        k = self.N if name in ("rho", "x") else self.dim
+        k = {"rho": self.N, "x": self.N, "u": self.dim}.get(name, self.N * self.dim)
         off = self.field_offsets[lattice] * k
         n = self.nodes[lattice] * k
-        return out[name][off: off + n].view(k, p.nz, p.ny, p.nx)
+        v = out[name][off: off + n]
+        if name in ("ueq", "us"):
+            return v.view(self.N, self.dim, p.nz, p.ny, p.nx)
+        return v.view(k, p.nz, p.ny, p.nx)
 
     def restore(self, cur, prev, t):
         check(lib.lbm_mc_restore(self.ctx, _ptr(cur), _ptr(prev), int(t)))
@@ -247,6 +241,23 @@ class LbmMc:
         """Reverse n steps through rows 0..n-1 of states (= s(t0) .. s(t0+n-1))."""
         check(lib.lbm_mc_adjoint_run(self.ctx, _ptr(states), states.stride(0), int(n),
                                      _ptr(lam_in), _ptr(lam_out), _ptr(grad)))
+
+    # ---------------------------------------------------------------- profile
+    def profile(self, state=None, out=None):
+        """Mole-fraction profile along x, averaged over y and z, of a stored
+        state (default: the current buffer): float64 [N, nx] on the device."""
+        state = self.buffers()[0] if state is None else state
+        p = self.params[0]
+        if out is None:
+            out = torch.empty((self.N, p.nx), dtype=torch.float64, device=self.device)
+        check(lib.lbm_mc_profile(self.ctx, _ptr(state), _ptr(out)))
+        return out
+
+    def profile_vjp(self, state, dxbar, lam):
+        """lam <- (d profile / d state)^T dxbar (dxbar float64 [N, nx] on the
+        device; lam a float32 buffer of the population layout)."""
+        dxbar = dxbar.to(device=self.device, dtype=torch.float64).contiguous()
+        check(lib.lbm_mc_profile_vjp(self.ctx, _ptr(state), _ptr(dxbar), _ptr(lam)))
 
     def close(self):
         if self.ctx:

@@ -267,8 +267,8 @@ def _gpu_gradient(ev, prob, target):
     adj = _adj()
     pairs = torch.tensor(_pairs(ev), dtype=torch.float64, requires_grad=True)
     g = torch.tensor(ev.g, dtype=torch.float64, requires_grad=True)
-    s = adj.evolve(pairs, g, prob)
-    L = adj.profile_misfit(s, ev.masses, 9, torch.as_tensor(target, device=s.device))
+    xbar = adj.evolve(pairs, g, prob)
+    L = adj.profile_misfit(xbar, torch.as_tensor(target, device=xbar.device))
     L.backward()
     return L.item(), pairs.grad.tolist(), g.grad.tolist()
 

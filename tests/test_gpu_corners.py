@@ -11,6 +11,7 @@ import torch
 import lbm_workloads as W
 from oracle import evd
 from oracle.lattice import DTYPE
+from tests._decode import populations
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +84,7 @@ def test_boxes_match_oracle(w, variant):
     out = sim.moments()
     sim.sync()
     dx = (sim.field(out, "x").double().cpu() - ob["x"]).abs().max().item()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     df = ((fg - ft).abs().max() / ft.abs().max()).item()
     drift = np.abs(out["mass"][0] / m0 - 1).max()
     dmass = np.abs(out["mass"][0] / ob["mass"].numpy() - 1).max()

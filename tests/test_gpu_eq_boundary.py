@@ -17,6 +17,7 @@ import torch
 import lbm_workloads as W
 from oracle import evd
 from oracle.lattice import DTYPE
+from tests._decode import populations
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +98,7 @@ def test_equilibrium_boundary_matches_oracle(w):
     out = sim.moments()
     sim.sync()
     dx = (sim.field(out, "x").double().cpu() - ob["x"]).abs().max().item()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     df = ((fg - ft).abs().max() / ft.abs().max()).item()
     dmass = np.abs(out["mass"][0] / ob["mass"].numpy() - 1).max()
     sim.close()
@@ -167,10 +168,10 @@ def test_equilibrium_boundary_keeps_a_uniform_rest_state():
     x0 = np.zeros_like(w.x0())
     x0[:] = np.array([0.1, 0.2, 0.3, 0.4])[:, None, None, None]
     sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
-    a = sim.populations("cur").clone()
+    a = populations(sim).clone()
     sim.step(50)
     sim.sync()
-    b = sim.populations("cur")
+    b = populations(sim)
     sim.close()
     assert ((b - a).abs().max() / a.abs().max()).item() < 1e-6
 

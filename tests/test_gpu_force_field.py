@@ -17,6 +17,7 @@ import torch
 import lbm_workloads as W
 from oracle import closed_forms, evd
 from oracle.lattice import DTYPE
+from tests._decode import populations
 
 pytestmark = pytest.mark.gpu
 
@@ -111,7 +112,7 @@ def test_force_field_matches_oracle(w, variant):
     out = sim.moments()
     sim.sync()
     dx = (sim.field(out, "x").double().cpu() - ob["x"]).abs().max().item()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     df = ((fg - ft).abs().max() / ft.abs().max()).item()
     drift = np.abs(out["mass"][0] / m0 - 1).max()
     # the observables' velocity also takes the field (u_i^eq = j/rho + k/2)
@@ -137,8 +138,8 @@ def test_uniform_field_equals_constant_force():
     b = lbm.LbmMc(lbm.params_from_workload(w0), w.x0(), accel=acc)
     a.step(50)
     b.step(50)
-    pa = a.populations("cur")
-    pb = b.populations("cur")
+    pa = populations(a, "cur")
+    pb = populations(b, "cur")
     a.sync()
     b.sync()
     assert torch.equal(pa, pb)

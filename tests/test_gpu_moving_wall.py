@@ -13,6 +13,7 @@ import torch
 import lbm_workloads as W
 from oracle import evd
 from oracle.lattice import DTYPE
+from tests._decode import populations
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +87,7 @@ def test_moving_walls_match_oracle(w, variant):
     dx = (sim.field(out, "x").double().cpu() - ob["x"]).abs().max().item()
     du = (sim.field(out, "u").double().cpu()
           - ob["u"].permute(3, 0, 1, 2)[:sim.dim]).abs().max().item()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     df = ((fg - ft).abs().max() / ft.abs().max()).item()
     drift = np.abs(out["mass"][0] / m0 - 1).max()
     sim.close()

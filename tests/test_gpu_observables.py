@@ -1,0 +1,167 @@
+"""GPU parity of the observables (through the C ABI) against the FP64 oracle:
+the species velocities u_i^eq and the real species velocity of eq. (CE_EQ83),
+the FP64 momentum totals, the mole-fraction profile of a stored state and its
+vector-Jacobian product.
+
+Bars: species velocities within 1e-6 absolute plus 1e-3 of the species'
+largest velocity (FP32 state of a few dozen steps; the velocity of a trace
+species, x = 0.001 in the paper's gases, is its small momentum divided by its
+small density, so its error is relative to its own scale); momentum totals within 1e-4 of
+sum_x rho |u| (the FP64 sum of FP32 node values); profiles within 1e-5 in mole
+fraction (the state's FP32 rounding); the profile's vector-Jacobian product
+within 1e-6 of the largest entry (FP64 arithmetic rounded to FP32)."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_workloads as W
+from oracle import evd
+from oracle.lattice import DTYPE
+from tests._decode import mole_fractions
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-6
+X_TOL = 1e-5
+
+
+def _lbm():
+    from paper_2504_07059_amd import lbm
+    return lbm
+
+
+def _announce(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+def _wk(name, lattice, shape, masses, walls, g, steps=20, seed=13, diff=None, kind="random",
+        x0_args=None):
+    N = len(masses)
+    if diff is None:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(0.05, 0.1, size=(N, N))
+        diff = ((d + d.T) / 2).tolist()
+    return W.Workload(name, lattice, *shape, masses, diff, 1.0, list(g), list(walls), steps,
+                      kind, seed=seed, x0_args=x0_args or {})
+
+
+CASES = [
+    _wk("d2q9_n3_xwall_gases", "D2Q9", (150, 9, 1), [2.0, 28.0, 44.0], (True, False, False),
+        (2e-5, 0, 0), kind="halves",
+        diff=W.pairs_to_matrix(W.load_accepted()["ternary_gravity"]["pairs"], 3)),
+    _wk("d2q9_n4_periodic", "D2Q9", (70, 21, 1), [1.0, 2.0, 3.0, 4.0], (False, False, False),
+        (3e-5, -1e-5, 0)),
+    _wk("d3q19_n4_zwall", "D3Q19", (20, 13, 17), [1.0, 2.0, 3.0, 4.0], (False, False, True),
+        (0, 1e-5, -2e-5), steps=12),
+    _wk("d3q19_n2_xwall", "D3Q19", (23, 9, 7), [1.0, 5.0], (True, False, False), (2e-5, 0, 0),
+        steps=12),
+]
+
+
+def _oracle(w, x0=None):
+    m = evd.Model(w.lattice, w.nx, w.ny, w.nz, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                  w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+    x0 = w.x0() if x0 is None else x0
+    f = evd.run(m, evd.initial_populations(m, torch.tensor(x0, dtype=DTYPE)), w.steps)
+    return m, evd.observables(m, f)
+
+
+def _velocity_check(w, x0=None):
+    lbm = _lbm()
+    m, ob = _oracle(w, x0)
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0() if x0 is None else x0)
+    sim.step(w.steps)
+    out = sim.moments(velocities=True)
+    sim.sync()
+    d = sim.dim
+    ueq = sim.field(out, "ueq").double().cpu()                    # [N, d, nz, ny, nx]
+    us = sim.field(out, "us").double().cpu()
+    ref_ueq = ob["ueq"].permute(0, 4, 1, 2, 3)[:, :d]
+    ref_us = ob["u_i"].permute(0, 4, 1, 2, 3)[:, :d]
+
+    def excess(a, b):
+        # largest error over the species of |a - b| - 1e-3 max|b| (per species)
+        err = (a - b).abs().flatten(1).max(dim=1).values
+        return (err - 1e-3 * b.abs().flatten(1).max(dim=1).values).max().item()
+    mom = out["momentum"][0]
+    ref_mom = (ob["rho"][..., None] * ob["u"]).sum(dim=(0, 1, 2))[:d].numpy()
+    scale = (ob["rho"][..., None] * ob["u"].abs()).sum(dim=(0, 1, 2))[:d].numpy()
+    sim.close()
+    print(f"max |d u_eq| {(ueq - ref_ueq).abs().max().item():.2e}, "
+          f"max |d u_i| {(us - ref_us).abs().max().item():.2e}")
+    return excess(ueq, ref_ueq), excess(us, ref_us), np.abs(mom - ref_mom), scale, ob
+
+
+@pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
+def test_species_velocities_match_oracle(w):
+    """u_i^eq and u_i = u_i^eq - Theta_i/(2 rho_i) at every node, and the FP64
+    momentum totals sum_x rho u, against the oracle."""
+    _announce(f"velocities {w.name}")
+    due, dus, dmom, scale, ob = _velocity_check(w)
+    assert due < U_TOL, due
+    assert dus < U_TOL, dus
+    assert (dmom <= 1e-4 * scale + 1e-12).all(), (dmom, scale)
+    # the real velocities differ from the equilibrium ones by more than the bar
+    assert (ob["u_i"] - ob["ueq"]).abs().max().item() > 10 * U_TOL
+
+
+def test_absent_species_velocity_is_the_limit():
+    """A species absent everywhere takes u_i^eq = g/2 (reading R4) and the
+    real velocity's limit (reading R12), as in the oracle."""
+    w = CASES[1]
+    _announce(f"absent species velocity {w.name}")
+    x0 = w.x0().copy()
+    x0[2] = 0.0
+    x0 /= x0.sum(axis=0, keepdims=True)
+    due, dus, dmom, scale, ob = _velocity_check(w, x0)
+    assert due < U_TOL, due
+    assert dus < U_TOL, dus
+    assert float(ob["rho_i"][2].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
+def test_profile_matches_oracle_and_moments(w):
+    """lbm_mc_profile of the current state against the oracle's mole
+    fractions averaged over y and z, and against the mean of lbm_mc_moments' x
+    at the same step (the state's densities are those of f(t))."""
+    lbm = _lbm()
+    _announce(f"profile {w.name}")
+    m, ob = _oracle(w)
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    sim.step(w.steps)
+    xbar = sim.profile().cpu()
+    out = sim.moments()
+    xm = sim.field(out, "x").double().cpu().mean(dim=(1, 2))
+    xs = mole_fractions(sim.raw("cur").cpu(), w.masses).mean(dim=(1, 2))
+    sim.sync()
+    sim.close()
+    ref = ob["x"].mean(dim=(1, 2))
+    assert (xbar - ref).abs().max().item() < X_TOL
+    assert (xbar - xm).abs().max().item() < 1e-6
+    assert (xbar - xs).abs().max().item() < 1e-12
+
+
+@pytest.mark.parametrize("w", CASES, ids=[w.name for w in CASES])
+def test_profile_vjp_matches_autograd(w):
+    """lbm_mc_profile_vjp against reverse mode (torch autograd, FP64) through
+    the test-side decoding of the state, for a random cotangent; the row
+    padding of the output is untouched."""
+    lbm = _lbm()
+    _announce(f"profile vjp {w.name}")
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    sim.step(3)
+    state = sim.buffers()[0].clone()
+    gen = torch.Generator().manual_seed(4)
+    dxbar = torch.randn((w.n_species, w.nx), generator=gen, dtype=torch.float64)
+    lam = torch.full_like(state, 7.0)
+    sim.profile_vjp(state, dxbar.cuda(), lam)
+    got = sim.view(lam).double().cpu()
+    pad_untouched = bool((lam.view(-1)[: sim.total].cpu() == 7.0).sum().item()
+                         == sim.total - got.numel())
+    s = sim.view(state).double().cpu().requires_grad_()
+    sim.sync()
+    sim.close()
+    (mole_fractions(s, w.masses).mean(dim=(1, 2)) * dxbar).sum().backward()
+    ref = s.grad
+    assert ((got - ref).abs().max() / ref.abs().max()).item() < 1e-6
+    assert pad_untouched

@@ -16,6 +16,7 @@ import torch
 import lbm_workloads as W
 from oracle import evd
 from oracle.lattice import DTYPE
+from tests._decode import populations
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +63,7 @@ def _compare(w, steps, tuning=None, ftol=F_RTOL):
     sim, out, m0 = _gpu_run(w, steps, tuning)
     xg = sim.field(out, "x").double().cpu()
     dx = (xg - ob["x"]).abs().max().item()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     df = ((fg - ft).abs().max() / ft.abs().max()).item()
     drift = np.abs(out["mass"][0] / m0 - 1).max()
     dmass = np.abs(out["mass"][0] / ob["mass"].numpy() - 1).max()
@@ -166,13 +167,13 @@ def test_execution_shape_does_not_change_results(tuning):
     variant = tuning[4] if len(tuning) > 4 else 0
     ref_shape = (256, 1, 16, 0, 0) if variant == 0 else (64, 1, 4, 0, 1)
     ref, _, _ = _gpu_run(w, 9, tuning=ref_shape)
-    a = ref.populations("cur").clone()
+    a = populations(ref, "cur").clone()
     sim, _, _ = _gpu_run(w, 9, tuning=tuning)
-    b = sim.populations("cur")
+    b = populations(sim)
     assert torch.equal(a, b)
     if variant == 1:
         other, _, _ = _gpu_run(w, 9, tuning=(256, 1, 16, 0, 0))
-        c = other.populations("cur")
+        c = populations(other, "cur")
         assert ((c - b).abs().max() / c.abs().max()).item() < F_RTOL
 
 
@@ -188,7 +189,7 @@ def test_determinism_and_resume_are_bitwise():
     b = lbm.LbmMc(p, w.x0())
     b.restore(cur, prev, 10)
     b.step(7)
-    assert torch.equal(a.populations("cur"), b.populations("cur"))
+    assert torch.equal(populations(a, "cur"), populations(b, "cur"))
     ma, mb = a.moments(), b.moments()
     assert torch.equal(ma["x"], mb["x"])
     assert np.array_equal(ma["mass"], mb["mass"])
@@ -303,7 +304,7 @@ def test_absent_species_match_oracle(where, w, variant):
         else ((16, 4, 3, 0, 1) if variant else (16, 4, 3, 0, 0))
     sim, out, m0 = _gpu_run(w, w.steps, shape, x0=x0)
     xg = sim.field(out, "x").double().cpu()
-    fg = sim.populations("cur").double().cpu()
+    fg = populations(sim).double().cpu()
     sim.close()
     assert (xg - ob["x"]).abs().max().item() < X_TOL
     assert ((fg - ft).abs().max() / ft.abs().max()).item() < F_RTOL
@@ -359,10 +360,10 @@ def test_graph_lengths_and_prepare_do_not_change_results():
     _announce(f"{w.name} graph lengths")
     lbm = _lbm()
     a = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
-    before = a.populations("cur").clone()
+    before = populations(a, "cur").clone()
     a.prepare(1100)
     a.sync()
-    assert a.t == 0 and torch.equal(a.populations("cur"), before)
+    assert a.t == 0 and torch.equal(populations(a, "cur"), before)
     a.step(1100)
     b = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
     for _ in range(1100 // 7):
@@ -371,7 +372,7 @@ def test_graph_lengths_and_prepare_do_not_change_results():
     a.sync()
     b.sync()
     assert a.t == b.t == 1100
-    assert torch.equal(a.populations("cur"), b.populations("cur"))
-    assert torch.equal(a.populations("prev"), b.populations("prev"))
+    assert torch.equal(populations(a, "cur"), populations(b, "cur"))
+    assert torch.equal(populations(a, "prev"), populations(b, "prev"))
     a.close()
     b.close()
