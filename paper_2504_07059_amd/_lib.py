@@ -77,3 +77,8 @@ def check(status):
     if status != OK:
         raise LbmError(status, lib.lbm_mc_last_error().decode())
     return status
+
+
+lib.lbm_mc_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, c_int64, c_int32,
+                                   ctypes.c_void_p]
+lib.lbm_mc_stream_copy.restype = c_int32

@@ -76,6 +76,92 @@ def layer_mixing_3d_small():
     return {"workload": w.name, "steps": w.steps, "checkpoints": out}
 
 
+def layer_mixing_3d_64():
+    """D3Q19 layer workload on a 64x32x32 box (z walls, interface at z = 24,
+    seeded 1 % perturbation): the whole mole-fraction field at 100, 1000 and
+    5000 steps, stored as float32 (its rounding, 6e-8, is far below the 1e-5
+    parity bar) in a compressed npz next to this file."""
+    w = W.layer_mixing_3d(64, 32, 32, steps=5000)
+    m = evd.Model(w.lattice, w.nx, w.ny, w.nz, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                  w.tau1, g=w.g, walls=w.walls, n0=w.n0)
+    f = evd.initial_populations(m, torch.tensor(w.x0(), dtype=DTYPE))
+    arrays, t, t0 = {}, 0, time.time()
+    for cp in (100, 1000, 5000):
+        with torch.no_grad():
+            while t < cp:
+                n = min(100, cp - t)
+                f = evd.run(m, f, n)
+                t += n
+                print(f"  t={t} ({time.time() - t0:.0f} s)", flush=True)
+        ob = evd.observables(m, f)
+        arrays[f"x_{cp}"] = ob["x"].numpy().astype(np.float32)
+        arrays[f"mass_{cp}"] = ob["mass"].numpy()
+    np.savez_compressed(os.path.join(HERE, "layer_mixing_3d_64x32x32.npz"),
+                        workload=np.array(w.name), **arrays)
+    return None
+
+
+BATCH_SAMPLE = (0, 168, 206, 378, 444, 511)   # first, longest, shortest, strongest g,
+                                              # heaviest, last tube
+
+
+def batched_sample():
+    """Six tubes of the 512-tube batch (first and last, the longest and the
+    shortest, the strongest gravity, the heaviest third species), each run on
+    one row for the batch's 10,000 steps; x at 1000 and 10,000 steps."""
+    tubes = W.batched_tubes()
+    out = {}
+    for k in BATCH_SAMPLE:
+        print(f" tube {k}", flush=True)
+        out[str(k)] = run_tube(tubes[k], [1000, 10000])
+    return {"workload": "batched_512_ternary_tubes", "steps": 10000, "tubes": out}
+
+
+HYPS = dict(nx=64, g=1e-5, x_mean=(0.4005, 0.249, 0.3505), steps=120000)
+
+
+def hypsometric_model():
+    """Ternary tube of the paper's gases' masses (2:28:44) with the seeded
+    diffusivities of the 1024x64 workload, walls at the x ends, one row,
+    gravity g along +x (ten times the workload's, so that the heaviest
+    species' density varies by 4 % over the 64 nodes)."""
+    w = W.ternary_gravity()
+    return evd.Model("D2Q9", HYPS["nx"], 1, 1, w.masses, torch.tensor(w.diff, dtype=DTYPE),
+                     w.tau1, g=[HYPS["g"], 0.0, 0.0], walls=(True, False, False))
+
+
+def hypsometric_walls():
+    """Stationary state of the hypsometric tube: started at the closed form
+    rho_i(x) = A_i exp(g x/c_{s,i}^2) (eq. MS_equation with k_i = g and eq.
+    NSE at rest, with p_i = rho_i c_{s,i}^2) of a uniform mean composition,
+    run until the state no longer changes (120,000 steps); stores the
+    post-stream populations f and the last 10,000 steps' largest change in x."""
+    from oracle import closed_forms
+    m = hypsometric_model()
+    nx, g = HYPS["nx"], HYPS["g"]
+    M = np.array(m.M)
+    xs = np.arange(nx, dtype=float)
+    n0 = m.default_n0()
+    mass = np.array(HYPS["x_mean"]) * M * n0 * nx
+    rho = closed_forms.hypsometric_densities(list(M), mass, np.stack([xs, 0 * xs, 0 * xs], 1),
+                                             [g, 0.0, 0.0])
+    n = (rho / M[:, None]).sum(0)
+    x = rho / M[:, None] / n
+    f = evd.initial_populations(m, torch.tensor(x)[:, None, None, :])
+    f = f * torch.tensor(n / n0)[None, None, None, None, :]
+    t0, t, last = time.time(), 0, None
+    while t < HYPS["steps"]:
+        with torch.no_grad():
+            f = evd.run(m, f, 10000)
+        t += 10000
+        xn = evd.observables(m, f)["x"][:, 0, 0, :]
+        change = None if last is None else float((xn - last).abs().max())
+        last = xn
+        print(f"  t={t} change {change} ({time.time() - t0:.0f} s)", flush=True)
+    return {"workload": "hypsometric_walls_64", "nx": nx, "g": g, "x_mean": HYPS["x_mean"],
+            "steps": t, "change_last_10000": change, "f": f[:, :, 0, 0, :].tolist()}
+
+
 def adjoint_tube():
     """Adjoint workload: target profile from the true diffusivities, then the
     misfit and its gradient at the evaluation point by reverse mode (segments
@@ -101,13 +187,19 @@ def adjoint_tube():
 
 
 JOBS = {"ternary_gravity": ternary_gravity, "binary_erf": binary_erf,
-        "adjoint_tube": adjoint_tube, "layer_mixing_3d_small": layer_mixing_3d_small}
+        "adjoint_tube": adjoint_tube, "layer_mixing_3d_small": layer_mixing_3d_small,
+        "layer_mixing_3d_64": layer_mixing_3d_64, "hypsometric_walls": hypsometric_walls,
+        "batched_sample": batched_sample}
 
 
 def main(names):
     for n in names or JOBS:
+        if "torch_threads" in os.environ:
+            torch.set_num_threads(int(os.environ["torch_threads"]))
         print(n, flush=True)
         res = JOBS[n]()
+        if res is None:     # the job wrote its own file
+            continue
         res["_about"] = ("oracle (FP64) result written by tests/golden/make_golden.py; "
                          "x[species][x-node] on a one-row lattice")
         with open(os.path.join(HERE, f"{n}.json"), "w") as fh:

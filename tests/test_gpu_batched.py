@@ -214,3 +214,29 @@ def test_batch_with_force_fields_equals_single_runs(one_launch):
         assert torch.equal(sim.raw("cur", l), one.raw("cur")), l
         one.close()
     sim.close()
+
+
+def test_full_batch_10000_steps_matches_stored_oracle():
+    """The whole 512-tube batch for its configured 10,000 steps, one launch per
+    step at the default shape: six sampled tubes (first and last, longest and
+    shortest, strongest gravity, heaviest third species; stored FP64 oracle
+    results, one row each) within 1e-5 in mole fraction on every row, and
+    every tube's FP64 mass within 1e-6."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batched_sample.json")) as fh:
+        G = json.load(fh)["tubes"]
+    tubes = W.batched_tubes()
+    _announce("full batch, 10000 steps")
+    sim = _batch(tubes)
+    m0 = sim.moments(fields=False)["mass"].copy()
+    sim.step(10000)
+    out = sim.moments()
+    sim.sync()
+    assert np.abs(out["mass"] / m0 - 1).max() < MASS_TOL
+    for k, rec in G.items():
+        ref = np.array(rec["10000"]["x"])
+        x = sim.field(out, "x", lattice=int(k)).double().cpu().numpy()[:, 0]
+        err = np.abs(x - ref[:, None, :]).max()
+        assert err < X_TOL, (k, err)
+    sim.close()

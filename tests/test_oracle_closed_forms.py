@@ -264,3 +264,79 @@ def test_d3q19_shear_wave_decays_with_common_viscosity():
     amp = float((uz * torch.sin(kw * xx)).sum() * 2 / nx)
     nu = -math.log(amp / U) / (kw * kw * steps)
     assert abs(nu / ((tau1 - 0.5) / 3) - 1) < 0.01
+
+
+# --------------------------------------- hypsometric tube between walls
+def _hypsometric_golden():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "hypsometric_walls.json")) as fh:
+        return json.load(fh)
+
+
+def _hypsometric_model(G):
+    import lbm_workloads as W
+    w = W.ternary_gravity()
+    return evd.Model("D2Q9", G["nx"], 1, 1, w.masses, torch.tensor(w.diff, dtype=DTYPE), w.tau1,
+                     g=[G["g"], 0.0, 0.0], walls=(True, False, False))
+
+
+def test_hypsometric_tube_between_walls():
+    """The paper's gases' masses (2:28:44), the 1024x64 workload's seeded
+    diffusivities, walls at the x ends, g = 1e-5 along x, 64 nodes: the
+    stationary state that the oracle reaches from the closed form (stored by
+    tests/golden/make_golden.py after 120,000 steps) is
+      * a fixed point of the current oracle (1000 more steps change no mole
+        fraction by more than 1e-9);
+      * at rest in the interior (20 nodes from each wall: |u| < 1e-8) with
+        rho_i(x) = A_i exp(g x/c_{s,i}^2), the hypsometric closed form of eq.
+        (MS_equation) with k_i = g and eq. (NSE) at rest, p_i = rho_i c_{s,i}^2,
+        to 1e-7 in mole fraction (amplitudes A_i fitted: the wall layers hold
+        part of each species' mass);
+      * next to each wall, a layer that Appendix A's scheme leaves for c < 1:
+        the printed wall formulas return less than the full weight to the
+        reflected direction at a uniform rest state (1 - xi(1 - xi)/2 for the
+        right wall's alpha = 3), so the wall node keeps a stationary velocity
+        (|u| about 1.1e-2 here, the same at g = 0) and a composition offset
+        (5.7e-2 in mole fraction), alternating in sign and decaying by about a
+        factor 2 per node into the interior."""
+    G = _hypsometric_golden()
+    m = _hypsometric_model(G)
+    nx, g, k = G["nx"], G["g"], 20
+    f = torch.tensor(G["f"], dtype=DTYPE)[:, :, None, None, :]
+    ob = evd.observables(m, f)
+    x = ob["x"][:, 0, 0].numpy()
+    x_later = evd.observables(m, evd.run(m, f, 1000))["x"][:, 0, 0].numpy()
+    assert np.abs(x_later - x).max() < 1e-9
+    rho = ob["rho_i"][:, 0, 0].numpy()
+    cs2 = np.array(m.sound2())
+    xs = np.arange(nx, dtype=float)
+    shape = np.exp(g * xs[None] / cs2[:, None])
+    A = (rho[:, k:nx - k] / shape[:, k:nx - k]).mean(1)
+    fit = A[:, None] * shape
+    M = np.array(m.M)
+    x_fit = fit / M[:, None] / (fit / M[:, None]).sum(0)
+    dev = np.abs(x - x_fit).max(0)
+    assert dev[k:nx - k].max() < 1e-7
+    u = ob["u"][0, 0, :, 0].numpy()
+    assert np.abs(u[k:nx - k]).max() < 1e-8
+    # the heaviest species' interior profile varies by 4 %: the fit is not trivial
+    assert fit[2, nx - k - 1] / fit[2, k] - 1 > 0.5 * (np.exp(g * (nx - 2 * k) / cs2[2]) - 1)
+    # the wall layers, mirror images of each other
+    assert 5e-3 < abs(u[0]) < 2e-2 and np.sign(u[0]) == -np.sign(u[-1])
+    assert 1e-2 < dev[0] < 0.1 and 1e-2 < dev[-1] < 0.1
+    for j in range(12):
+        assert np.sign(u[j]) == -np.sign(u[j + 1])
+        assert 1.3 < abs(u[j] / u[j + 1]) < 3.0, j
+
+
+def test_wall_layer_does_not_come_from_gravity():
+    """The wall layer of the hypsometric tube is the same at g = 0: a uniform
+    mixture of the same masses at rest between walls develops it (wall-node
+    velocity within 1 % of the g = 1e-5 value after 3000 steps)."""
+    G = _hypsometric_golden()
+    m0 = _hypsometric_model(dict(G, g=0.0))
+    x0 = torch.tensor(G["x_mean"], dtype=DTYPE)[:, None, None, None].expand(3, 1, 1, G["nx"])
+    f = evd.run(m0, evd.initial_populations(m0, x0.clone()), 3000)
+    u0 = evd.observables(m0, f)["u"][0, 0, 0, 0].item()
+    m = _hypsometric_model(G)
+    u = evd.observables(m, torch.tensor(G["f"], dtype=DTYPE)[:, :, None, None, :])["u"][0, 0, 0, 0]
+    assert abs(u0 / u.item() - 1) < 1e-2
