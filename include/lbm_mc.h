@@ -312,6 +312,23 @@ lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* ctx, const float* lam0, double* gr
 lbm_mc_status lbm_mc_profile(lbm_mc_ctx* ctx, const float* state, double* xbar);
 
 /*
+ * lbm_mc_profile for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same profile, computed with the same kernels, whose FP64 partial sums live
+ * in a fixed device array of the library (4 MiB on each GPU it runs on, held
+ * until the process ends) instead of context memory.  The call allocates and
+ * frees nothing.  The array holds N * nx partial sums per chunk of rows:
+ * N * nx above 524288 is rejected (LBM_MC_ERR_INVALID) before any device
+ * work; below that the rows are split into at most 524288 / (N nx) chunks
+ * (the chunks of lbm_mc_profile whenever they fit, then the results are
+ * bit-identical to it).  Every context on one GPU shares that GPU's array, so
+ * calls that overlap in time on one GPU (different streams) race; calls in
+ * one stream are ordered.  Nothing in the array needs clearing between calls.
+ * Arguments and other errors as lbm_mc_profile.
+ */
+lbm_mc_status lbm_mc_profile_static(lbm_mc_ctx* ctx, const float* state, double* xbar);
+
+/*
  * Vector-Jacobian product of lbm_mc_profile at `state`: given
  * dxbar = dL/dxbar (device double [N][nx]), writes lam = dL/dstate (device
  * float, population layout) at every node: with d_i = dxbar_i(x),

@@ -54,6 +54,7 @@ def _load():
         "lbm_mc_replay": [vp, vp, c_int64, vp, c_int64],
         "lbm_mc_adjoint_run": [vp, vp, c_int64, c_int64, vp, vp, vp],
         "lbm_mc_profile": [vp, vp, vp],
+        "lbm_mc_profile_static": [vp, vp, vp],
         "lbm_mc_profile_vjp": [vp, vp, vp, vp],
         "lbm_mc_set_tuning": [vp, c_int32, c_int32, c_int32, c_int32, c_int32],
         "lbm_mc_get_tuning": [vp, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32)],

@@ -98,6 +98,10 @@ hipError_t launch_adjoint_init(int lattice, int nspecies, const LatParams* lp_de
 hipError_t launch_profile(int lattice, int nspecies, const LatParams* lp_dev,
                           const LatParams& lp_host, const float* state, int rows_per,
                           int nchunks, double* part, double* xbar, hipStream_t s);
+// the fixed device array of the allocation-free profile: its size in doubles
+// and its address on the current device (looked up once per device)
+constexpr int64_t kProfileScratchDoubles = (int64_t)1 << 19;   // 4 MiB
+hipError_t profile_scratch(double** out);
 hipError_t launch_profile_vjp(int lattice, int nspecies, const LatParams* lp_dev,
                               const LatParams& lp_host, const float* state, const double* dxbar,
                               float* lam, int max_blocks, hipStream_t s);

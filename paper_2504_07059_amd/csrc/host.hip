@@ -437,6 +437,8 @@ struct lbm_mc_ctx {
     // profile partial sums [chunks][N][nx] (allocated on first use)
     double* dprof = nullptr;
     size_t dprof_cap = 0;
+    // the fixed scratch array of lbm_mc_profile_static on this context's device
+    double* static_scratch = nullptr;
 };
 
 namespace {
@@ -879,6 +881,8 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "no HIP device"));
     hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (profile_scratch(&c->static_scratch) != hipSuccess)
+        return bail(fail(LBM_MC_ERR_HIP, "device address of the profile scratch"));
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(LBM_MC_ERR_HIP, "stream create failed"));
 
@@ -1283,6 +1287,29 @@ lbm_mc_status lbm_mc_profile(lbm_mc_ctx* c, const float* state, double* xbar) {
     }
     HIPCHECK(launch_profile(c->lattice, c->N, c->dlp, c->hlp[0], state, rows_per, nchunks,
                             c->dprof, xbar, c->stream));
+    return LBM_MC_OK;
+}
+
+lbm_mc_status lbm_mc_profile_static(lbm_mc_ctx* c, const float* state, double* xbar) {
+    lbm_mc_status st = profile_check(c, state, xbar);
+    if (st != LBM_MC_OK) return st;
+    const int64_t per_chunk = (int64_t)c->N * c->params[0].nx;
+    if (per_chunk > kProfileScratchDoubles)
+        return fail(LBM_MC_ERR_INVALID,
+                    "profile_static: N * nx = %lld exceeds the fixed scratch of %lld doubles",
+                    (long long)per_chunk, (long long)kProfileScratchDoubles);
+    // the same row chunks as lbm_mc_profile (bit-identical results) unless
+    // they do not fit the array, then fewer, longer chunks
+    int rows_per, nchunks;
+    profile_chunks(c, rows_per, nchunks);
+    if ((int64_t)nchunks * per_chunk > kProfileScratchDoubles) {
+        const int64_t rows = (int64_t)c->params[0].ny * c->params[0].nz;
+        const int64_t cap = kProfileScratchDoubles / per_chunk;
+        rows_per = (int)((rows + cap - 1) / cap);
+        nchunks = (int)((rows + rows_per - 1) / rows_per);
+    }
+    HIPCHECK(launch_profile(c->lattice, c->N, c->dlp, c->hlp[0], state, rows_per, nchunks,
+                            c->static_scratch, xbar, c->stream));
     return LBM_MC_OK;
 }
 

@@ -16,10 +16,19 @@
 // chunk order.  The result does not depend on timing (no atomics).
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 #include "lattice.hpp"
 
 namespace lbmmc {
+
+// Scratch of the allocation-free profile (lbm_mc_profile_static): the FP64
+// partial sums live in this fixed device array instead of context memory.
+// Host code never uses the array's name as an address: profile_scratch()
+// looks up each device's copy with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kProfileScratchDoubles];
 
 // Species densities (FP64) of node (x, row) of a lattice's stored state.
 template <int LAT, int NS>
@@ -172,6 +181,26 @@ hipError_t launch_profile_vjp(int lattice, int ns, const LatParams* lp, const La
                            dxbar, lam);
         return hipGetLastError();
     });
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept for the process.
+hipError_t profile_scratch(double** out) {
+    static std::mutex mu;
+    static std::map<int, double*> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        double* p = nullptr;
+        e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 }  // namespace lbmmc

@@ -253,6 +253,16 @@ class LbmMc:
         check(lib.lbm_mc_profile(self.ctx, _ptr(state), _ptr(out)))
         return out
 
+    def profile_static(self, state=None, out=None):
+        """profile() through the allocation-free entry point (its partial sums
+        in the library's fixed device array)."""
+        state = self.buffers()[0] if state is None else state
+        p = self.params[0]
+        if out is None:
+            out = torch.empty((self.N, p.nx), dtype=torch.float64, device=self.device)
+        check(lib.lbm_mc_profile_static(self.ctx, _ptr(state), _ptr(out)))
+        return out
+
     def profile_vjp(self, state, dxbar, lam):
         """lam <- (d profile / d state)^T dxbar (dxbar float64 [N, nx] on the
         device; lam a float32 buffer of the population layout)."""
