@@ -128,9 +128,10 @@ def roofline(name, per_launch_bytes, ms, steps, tuning=None, ceiling=None, bound
 
 
 # ------------------------------------------------------------ streaming copy
-def copy_sweep(sizes_gib=(1, 2, 4), blocks_per_cu=(1, 2, 4, 8, 16), reps=5):
+def copy_sweep(sizes_gib=(1, 2, 4), blocks_per_cu=(1, 2, 4, 8), reps=5):
     """The streaming copy of this build over buffer sizes and grid sizes: the
-    best read+write rate is the practical ceiling of a read-one-write-one
+    best read+write rate over buffers of 2 GiB and more (well beyond the
+    256 MB last-level cache) is the practical ceiling of a read-one-write-one
     kernel."""
     import ctypes
     import torch
@@ -158,7 +159,8 @@ def copy_sweep(sizes_gib=(1, 2, 4), blocks_per_cu=(1, 2, 4, 8, 16), reps=5):
             ms = e0.elapsed_time(e1) / reps
             gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
             rows.append({"GiB": gib, "blocks": blocks, "us": ms * 1e3, "GBs": gbs})
-            best = max(best, gbs)
+            if gib >= 2:
+                best = max(best, gbs)
         assert torch.equal(a[:1024], b[:1024]) and torch.equal(a[-1024:], b[-1024:])
         del a, b
         torch.cuda.empty_cache()
@@ -603,7 +605,7 @@ def main():
         return
 
     t_start = time.perf_counter()
-    copy = copy_sweep(sizes_gib=(1, 4), blocks_per_cu=(2, 4, 8, 16))
+    copy = copy_sweep()
     bt = time_batched(args.steps, args.warmup, modes=(1,), tuning=fixed)
     ms = bt["ms"][1]
     tune = bt["tuning"]

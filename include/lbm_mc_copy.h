@@ -18,7 +18,7 @@ extern "C" {
 /*
  * dst[0 .. n_floats) = src[0 .. n_floats), asynchronously on hip_stream
  * (NULL = null stream), with `blocks` work-groups of 256 threads in a
- * grid-stride loop (16-byte loads, non-temporal 16-byte stores).
+ * grid-stride loop (non-temporal 16-byte loads and stores).
  *   src, dst   device memory, 16-byte aligned, not overlapping; caller-owned.
  *   n_floats   a multiple of 4, >= 0.
  * Returns 0 on success, 1 (LBM_MC_ERR_INVALID) for a bad argument, 3

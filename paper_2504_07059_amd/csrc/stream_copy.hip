@@ -1,7 +1,9 @@
 // A streaming device copy used as the read-write reference of the benchmark:
-// it moves every byte once in each direction, with 16-byte loads and
-// non-temporal 16-byte stores, over a grid-stride loop with four independent
-// transfers in flight per thread.  Its rate is the practical ceiling of a
+// it moves every byte once in each direction, with non-temporal 16-byte loads
+// and stores, over a grid-stride loop with four independent transfers in
+// flight per thread.  (Measured on MI355X: best with one 256-thread
+// work-group per compute unit; more work-groups interleave more streams and
+// lose bandwidth, plain loads or stores lose a few per cent.)  Its rate is the practical ceiling of a
 // kernel that reads one array and writes another of the same size, and its
 // FETCH_SIZE / WRITE_SIZE counters calibrate those of the fused step.
 #include <hip/hip_runtime.h>
@@ -17,16 +19,16 @@ __global__ void __launch_bounds__(256) k_stream_copy(const f4* __restrict__ src,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i + 3 * stride < n4; i += 4 * stride) {
-        const f4 a = src[i];
-        const f4 b = src[i + stride];
-        const f4 c = src[i + 2 * stride];
-        const f4 d = src[i + 3 * stride];
+        const f4 a = __builtin_nontemporal_load(src + i);
+        const f4 b = __builtin_nontemporal_load(src + i + stride);
+        const f4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const f4 d = __builtin_nontemporal_load(src + i + 3 * stride);
         __builtin_nontemporal_store(a, dst + i);
         __builtin_nontemporal_store(b, dst + i + stride);
         __builtin_nontemporal_store(c, dst + i + 2 * stride);
         __builtin_nontemporal_store(d, dst + i + 3 * stride);
     }
-    for (; i < n4; i += stride) __builtin_nontemporal_store(src[i], dst + i);
+    for (; i < n4; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace
