@@ -500,12 +500,12 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def sub_tube_hbm(copy_best, variants=True):
+def sub_tube_hbm(copy_best, variants=True, tuning=None):
     import dataclasses
     import torch
     w = workload("c1_hbm")
     steps = 500
-    ms, drift, tune = time_lattice(w, steps, 20)
+    ms, drift, tune = time_lattice(w, steps, 20, tuning=tuning)
     per = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     rec = {"workload": w.name, "steps": steps, "tuning": tune,
            "value": w.nodes * w.n_species * steps / (ms * 1e3), "unit": UNIT,
@@ -535,10 +535,10 @@ def sub_tube_hbm(copy_best, variants=True):
     return rec
 
 
-def sub_tube_llc():
+def sub_tube_llc(tuning=None):
     w = workload("c1")
     steps = 2000
-    ms, drift, tune = time_lattice(w, steps, 200)
+    ms, drift, tune = time_lattice(w, steps, 200, tuning=tuning)
     per = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     return {"workload": w.name, "steps": steps, "tuning": tune,
             "value": w.nodes * w.n_species * steps / (ms * 1e3), "unit": UNIT,
@@ -549,10 +549,10 @@ def sub_tube_llc():
             "accuracy": tube_accuracy_vs_golden(w, tune)}
 
 
-def sub_layer_3d(copy_best):
+def sub_layer_3d(copy_best, tuning=None):
     w = workload("c2")
     steps = 200
-    ms, drift, tune = time_lattice(w, steps, 20)
+    ms, drift, tune = time_lattice(w, steps, 20, tuning=tuning)
     per = bytes_per_species_node(w.lattice) * w.nodes * w.n_species
     return {"workload": w.name, "steps": steps, "tuning": tune,
             "value": w.nodes * w.n_species * steps / (ms * 1e3), "unit": UNIT,
@@ -592,11 +592,11 @@ def main():
             mode = 1 if args.only == "batched" else 0
             res = time_batched(args.steps, args.warmup, modes=(mode,), tuning=fixed)
         elif args.only == "tube_hbm":
-            res = sub_tube_hbm(None, variants=False)
+            res = sub_tube_hbm(None, variants=False, tuning=fixed)
         elif args.only == "tube_llc":
-            res = sub_tube_llc()
+            res = sub_tube_llc(tuning=fixed)
         elif args.only == "layer_3d":
-            res = sub_layer_3d(None)
+            res = sub_layer_3d(None, tuning=fixed)
         elif args.only == "adjoint":
             res = time_adjoint()
         else:

@@ -368,8 +368,11 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t s
  * 2-D, and block_x * block_y is 64, 128, 192 or 256.  persistent: 0 = one
  * work-group per tile, > 0 = that many resident work-groups looping over the
  * tile list.  variant: 0 = one thread per column carrying every species;
- * 1 = one wavefront per species over 64 columns (block_x * block_y = 64), the
- * species exchanging their moments through LDS.  Both give the same results.
+ * 1 = one wavefront per species over each segment of 64 columns, the species
+ * exchanging their moments through LDS: block_x * block_y = 64 (one segment),
+ * or W = block_x * block_y / 64 segments (block_x a multiple of 64: W pieces
+ * of an x row, or W rows in 3-D) marching in step, with N * W <= 12.  Both
+ * variants give the same results.
  * Rebuilds the tile list and drops captured graphs.  0 for block_x, block_y
  * or rows, and -1 for persistent, keep the current value; variant -1 keeps
  * the current variant if the new shape allows it, else selects variant 0.

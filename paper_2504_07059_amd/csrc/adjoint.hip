@@ -206,123 +206,163 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
 }
 
 // ------------------------------------------------------------------ kernel B
-// lam_f(t-1)(X) = sum_k Lambda_k(e) mu(X - k) over fluid targets (the gather
-// with the velocity reversed: Lambda_{-k}(e) = Lambda_k(-e)), plus the
-// transposed wall terms; species 1 (c = 1): mu_a(X + c_a), or mu_abar(X)
-// where X + c_a is solid.  Stored as lam_s = T^-T lam_f:
-// lam_P0 = lam_f0 + sum_a (w_a/w_0) lam_fa, lam_ga = lam_fa.  One thread per
-// (column, species): species are independent here.
+// lam_f(t-1)(X) = sum_k Lambda_k(-e) mu(X + k) over fluid sources X + k (the
+// pull gather with the velocity reversed: Lambda_{-k}(e) = Lambda_k(-e)),
+// plus the transposed wall terms; species 1 (c = 1): mu_a(X + c_a), or
+// mu_abar(X) where X + c_a is solid.  Stored as lam_s = T^-T lam_f:
+// lam_P0 = lam_f0 + sum_a (w_a/w_0) lam_fa, lam_ga = lam_fa.
+// The same march as the forward gather: one wave per species over a tile's
+// columns, the cross-section passes read per layer (x neighbours across lanes
+// for 64-column rows), the pass along the marching axis carried in registers
+// (two partial sums per plane), so every value of mu is read about once.
+// Direction a reversed has the components of opp(a).
+#define LBM_HPR(CEN)                                                                      \
+    ((Fr::p0(La::opp(a)) > 0)                                                             \
+         ? ((Fr::p1(La::opp(a)) > 0)   ? hpass<LAT, 1, 1>(M, pidx, CEN, col, L, nb)        \
+            : (Fr::p1(La::opp(a)) < 0) ? hpass<LAT, 1, -1>(M, pidx, CEN, col, L, nb)       \
+                                       : hpass<LAT, 1, 0>(M, pidx, CEN, col, L, nb))       \
+     : (Fr::p0(La::opp(a)) < 0)                                                           \
+         ? ((Fr::p1(La::opp(a)) > 0)   ? hpass<LAT, -1, 1>(M, pidx, CEN, col, L, nb)       \
+            : (Fr::p1(La::opp(a)) < 0) ? hpass<LAT, -1, -1>(M, pidx, CEN, col, L, nb)      \
+                                       : hpass<LAT, -1, 0>(M, pidx, CEN, col, L, nb))      \
+         : ((Fr::p1(La::opp(a)) > 0)   ? hpass<LAT, 0, 1>(M, pidx, CEN, col, L, nb)        \
+            : (Fr::p1(La::opp(a)) < 0) ? hpass<LAT, 0, -1>(M, pidx, CEN, col, L, nb)       \
+                                       : hpass<LAT, 0, 0>(M, pidx, CEN, col, L, nb)))
+
+template <int LAT, int POL, class NB>
+__device__ __forceinline__ void adj_stream_column(const Buf& M, const Buf& O,
+                                                  const GatherConst& G, const ColGeom& g, int s,
+                                                  const float (&L)[3], int m0, int m1,
+                                                  bool inside, const NB& nb) {
+    using Fr = Frame<LAT>;
+    using La = Lat<LAT>;
+    constexpr int Q = La::Q;
+    constexpr int DIM = La::DIM;
+    const Col& col = g.col;
+    const int pb0 = s * Q;
+    float acc0[Q], acc1[Q];
+    if (s > 0) {
+        const unsigned cm_ = layer_off(g, nbr(m0, -1, G.nm, g.wm)), c0_ = layer_off(g, m0);
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            if (Fr::pm(a) != 0) {
+                const int pidx = pb0 + a;
+                const W3 wmar = wsel(-Fr::pm(a), L);
+                const float hm = LBM_HPR(cm_);
+                const float h0 = LBM_HPR(c0_);
+                acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
+                acc1[a] = wmar.m * h0;
+            } else {
+                acc0[a] = 0.0f;
+                acc1[a] = 0.0f;
+            }
+        }
+    }
+    for (int m = m0; m < m1; ++m) {
+        const int mp = nbr(m, 1, G.nm, g.wm);
+        const unsigned own = layer_off(g, m);
+        const unsigned nxt = layer_off(g, mp);
+        float lf[Q];
+        lf[0] = ldb(M, pb0, own);
+        if (s == 0) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                // source X + c_a (the reversed shift); where it is solid, the
+                // bounce-back transpose mu_abar(X)
+                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
+                unsigned src = own;
+                bool solid = false;
+                if (c0 > 0) { src += col.bxp; solid = solid || col.sxp; }
+                if (c0 < 0) { src += col.bxm; solid = solid || col.sxm; }
+                if constexpr (DIM == 3) {
+                    if (c1 > 0) { src += col.byp; solid = solid || col.syp; }
+                    if (c1 < 0) { src += col.bym; solid = solid || col.sym; }
+                }
+                if (cm != 0) {
+                    const int ms = nbr(m, cm, G.nm, g.wm);
+                    solid = solid || ms < 0;
+                    src += (unsigned)(ms - m) * g.lsb;
+                }
+                const int lo = a < La::opp(a) ? a : La::opp(a);
+                const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
+                                          : src + (unsigned)((a - lo) * M.pb);
+                lf[a] = ldb(M, lo, sg);
+            }
+        } else {
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                const int pidx = pb0 + a;
+                if (Fr::pm(a) == 0) {
+                    lf[a] = LBM_HPR(own);
+                } else {
+                    const W3 wmar = wsel(-Fr::pm(a), L);
+                    const float hn = LBM_HPR(nxt);   // 0 beyond a wall
+                    lf[a] = fmaf(wmar.p, hn, acc0[a]);
+                    acc0[a] = fmaf(wmar.z, hn, acc1[a]);
+                    acc1[a] = wmar.m * hn;
+                }
+            }
+            // transposed wall terms (walls on one axis): the forward adds
+            // lambda_+1 f~_a(X) + lambda_-1 f~_abar(X) to f_a(X) for a pointing
+            // away from the wall
+            const Sides sd = wall_sides<LAT>(G, g, m);
+            if (sd.any) {
+#pragma unroll
+                for (int a = 1; a < Q; ++a) {
+                    int away = 0, toward = 0;
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int p = sd.s[ax] * Fr::comp(a, ax);
+                        away += p < 0;
+                        toward += p > 0;
+                    }
+                    if (away) lf[a] = fmaf(L[2], ldb(M, pb0 + a, own), lf[a]);
+                    if (toward) lf[a] = fmaf(L[0], ldb(M, pb0 + La::opp(a), own), lf[a]);
+                }
+            }
+        }
+        if (inside) {
+            float lp0 = lf[0];
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                lp0 = fmaf(La::wr(a), lf[a], lp0);
+                stb<POL>(O, pb0 + a, own, lf[a]);
+            }
+            stb<POL>(O, pb0, own, lp0);
+        }
+    }
+}
+
+#undef LBM_HPR
+
 template <int LAT, int NS, int POL>
 __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu,
                                                     float* __restrict__ lamout,
                                                     const LatParams* __restrict__ lps,
                                                     const Tile* __restrict__ tiles, int bx) {
-    using Fr = Frame<LAT>;
-    using La = Lat<LAT>;
-    constexpr int DIM = La::DIM;
-    constexpr int Q = La::Q;
+    constexpr int DIM = Lat<LAT>::DIM;
+    constexpr int Q = Lat<LAT>::Q;
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
+    // lanes beyond the lattice run along (their neighbours across lanes are
+    // the row's last columns) and store nothing
     int x, y;
     bool zero;
-    if (!tile_column<LAT>(T, P, lane, bx, x, y, zero)) return;
+    const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
     const GatherConst G = gather_const(P, DIM);
+    ColGeom g = col_geom<LAT>(G, x, y);
+    if (zero) g.colbase += kSolid;
     const int64_t lf = P.plane * NS * Q;
     const Buf M = make_buf(mu + P.base, lf, P.plane);
     const Buf O = make_buf(lamout + P.base, lf, P.plane);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-    // (the reverse step is provided for at most one wall axis)
-    const bool wx = (G.walls & 1) != 0, wy = DIM == 3 && (G.walls & 2) != 0,
-               wm = (G.walls & (1 << Fr::MA)) != 0;
-    const int xm = nbr(x, -1, G.nx, wx), xp = nbr(x, 1, G.nx, wx);
-    int ym = 0, yp = 0;
-    if (DIM == 3) {
-        ym = nbr(y, -1, G.ny, wy);
-        yp = nbr(y, 1, G.ny, wy);
-    }
-    const unsigned bxo[3] = {xm < 0 ? kSolid : (unsigned)(xm - x) * 4u, 0u,
-                             xp < 0 ? kSolid : (unsigned)(xp - x) * 4u};
-    const unsigned byo[3] = {DIM == 3 ? (ym < 0 ? kSolid : (unsigned)((ym - y) * G.pitch) * 4u) : 0u,
-                             0u,
-                             DIM == 3 ? (yp < 0 ? kSolid : (unsigned)((yp - y) * G.pitch) * 4u) : 0u};
-    const int sx = wx ? (x == 0 ? -1 : (x == G.nx - 1 ? 1 : 0)) : 0;
-    const int sy = wy ? (y == 0 ? -1 : (y == G.ny - 1 ? 1 : 0)) : 0;
-    const unsigned colbase = (unsigned)((DIM == 2 ? 0 : y * G.pitch) + x) * 4u;
-    const unsigned lsb = (unsigned)G.lstride * 4u;
-    const int pb0 = s * Q;
-    for (int m = T.m0; m < T.m1; ++m) {
-        const int mmv = nbr(m, -1, G.nm, wm), mpv = nbr(m, 1, G.nm, wm);
-        const unsigned own = (unsigned)m * lsb + colbase;
-        const unsigned bmo[3] = {mmv < 0 ? kSolid : (unsigned)(mmv - m) * lsb, 0u,
-                                 mpv < 0 ? kSolid : (unsigned)(mpv - m) * lsb};
-        const int sm = wm ? (m == 0 ? -1 : (m == G.nm - 1 ? 1 : 0)) : 0;
-        const int axis = wx ? 0 : (wm ? Fr::MA : 1);
-        const int side = wx ? sx : (wm ? sm : sy);
-        float lf_[Q];
-        lf_[0] = ldb(M, pb0, own);
-        if (s == 0) {
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                // reversed shift: mu_a(X + c_a), or the bounce-back transpose
-                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
-                unsigned src = own;
-                bool solid = false;
-                if (c0 != 0) { src += bxo[1 + c0]; solid = solid || (c0 < 0 ? xm < 0 : xp < 0); }
-                if (DIM == 3 && c1 != 0) { src += byo[1 + c1]; solid = solid || (c1 < 0 ? ym < 0 : yp < 0); }
-                if (cm != 0) { src += bmo[1 + cm]; solid = solid || (cm < 0 ? mmv < 0 : mpv < 0); }
-                const int lo = a < La::opp(a) ? a : La::opp(a);
-                const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
-                                          : src + (unsigned)((a - lo) * M.pb);
-                lf_[a] = ldb(M, lo, sg);
-            }
-        } else {
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
-                // weights of the reversed velocity: offsets k' with Lambda_k'(-e)
-                const W3 wxw = wsel(-c0, L), wyw = wsel(-c1, L), wmw = wsel(-cm, L);
-                const float wxv[3] = {wxw.m, wxw.z, wxw.p};
-                const float wyv[3] = {wyw.m, wyw.z, wyw.p};
-                const float wmv[3] = {wmw.m, wmw.z, wmw.p};
-                float v = 0.0f;
-#pragma unroll
-                for (int km = -1; km <= 1; ++km) {
-                    if (cm == 0 && km != 0) continue;
-                    float vy = 0.0f;
-#pragma unroll
-                    for (int ky = -1; ky <= 1; ++ky) {
-                        if ((DIM == 2 || c1 == 0) && ky != 0) continue;
-                        float vx = 0.0f;
-#pragma unroll
-                        for (int kx = -1; kx <= 1; ++kx) {
-                            if (c0 == 0 && kx != 0) continue;
-                            const unsigned off = own + bmo[1 + km] + byo[1 + ky] + bxo[1 + kx];
-                            vx = fmaf(wxv[1 + kx], ldb(M, pb0 + a, off), vx);
-                        }
-                        vy = fmaf(wyv[1 + ky], vx, vy);
-                    }
-                    v = fmaf(wmv[1 + km], vy, v);
-                }
-                // transposed walls
-                if (side != 0) {
-                    const int ca = Fr::comp(a, axis);
-                    if (ca != 0) {
-                        if (side * ca < 0) v = fmaf(L[2], ldb(M, pb0 + a, own), v);
-                        else v = fmaf(L[0], ldb(M, pb0 + La::opp(a), own), v);
-                    }
-                }
-                lf_[a] = v;
-            }
-        }
-        float lp0 = lf_[0];
-#pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            lp0 = fmaf(La::wr(a), lf_[a], lp0);
-            stb<POL>(O, pb0 + a, own, lf_[a]);
-        }
-        stb<POL>(O, pb0, own, lp0);
+    if (bx == 64) {
+        const NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
+        adj_stream_column<LAT, POL>(M, O, G, g, s, L, T.m0, T.m1, inside, nb);
+    } else {
+        adj_stream_column<LAT, POL>(M, O, G, g, s, L, T.m0, T.m1, inside, NbLoad{});
     }
 }
 

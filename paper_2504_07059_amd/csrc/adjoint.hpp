@@ -14,8 +14,9 @@ __device__ __forceinline__ void tau_vjp(const float (&rho)[NS], float R, float n
                                         const CollConst& C, float (&dY)[NS][NS],
                                         float (&drho)[NS], float& dR, float& dn,
                                         float (&dK)[NS][NS]) {
-    // forward recomputation with the intermediates
-    float y[NS][NS], E[NS][NS], qv[NS], tv[NS];
+    // forward recomputation with the intermediates (the reciprocals as in
+    // the forward tau_solve: hardware reciprocal plus one Newton step)
+    float y[NS][NS], iE[NS][NS], qv[NS], tv[NS], iq[NS];
 #pragma unroll
     for (int j = NS - 1; j >= 1; --j) {
         float Rj = 2.0f * R;
@@ -24,35 +25,36 @@ __device__ __forceinline__ void tau_vjp(const float (&rho)[NS], float R, float n
         float q = 0.0f;
 #pragma unroll
         for (int i = 0; i < j; ++i) {
-            E[j][i] = fmaf(n, C.K[i][j], rho[j]);
-            q += rho[i] / E[j][i];
+            iE[j][i] = rcp_nr(fmaf(n, C.K[i][j], rho[j]));
+            q += rho[i] * iE[j][i];
         }
-        const float t = Rj / (1.0f + q);
+        iq[j] = rcp_nr(1.0f + q);
+        const float t = Rj * iq[j];
         qv[j] = q;
         tv[j] = t;
 #pragma unroll
         for (int i = 0; i < j; ++i) {
-            y[i][j] = t / E[j][i];
+            y[i][j] = t * iE[j][i];
             y[j][i] = y[i][j];
         }
     }
     // reverse, columns in ascending order
 #pragma unroll
     for (int j = 1; j < NS; ++j) {
-        const float t = tv[j], q = qv[j];
+        const float t = tv[j];
         float dt = 0.0f;
         float dE[NS];
 #pragma unroll
         for (int i = 0; i < j; ++i) {
-            dt += dY[i][j] / E[j][i];
-            dE[i] = -dY[i][j] * t / (E[j][i] * E[j][i]);
+            dt += dY[i][j] * iE[j][i];
+            dE[i] = -dY[i][j] * t * iE[j][i] * iE[j][i];
         }
-        const float dRj = dt / (1.0f + q);
-        const float dq = -dt * t / (1.0f + q);
+        const float dRj = dt * iq[j];
+        const float dq = -dt * t * iq[j];
 #pragma unroll
         for (int i = 0; i < j; ++i) {
-            drho[i] += dq / E[j][i];
-            dE[i] -= dq * rho[i] / (E[j][i] * E[j][i]);
+            drho[i] += dq * iE[j][i];
+            dE[i] -= dq * rho[i] * iE[j][i] * iE[j][i];
         }
 #pragma unroll
         for (int i = 0; i < j; ++i) {
@@ -91,7 +93,7 @@ __device__ __forceinline__ void vjp_forward(const float (&rho)[NS], const float 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         f.live[s] = fabsf(rho[s]) > kRhoTiny;
-        const float cr = f.live[s] ? C.c[s] / rho[s] : 0.0f;
+        const float cr = f.live[s] ? C.c[s] * rcp_nr(rho[s]) : 0.0f;
 #pragma unroll
         for (int d = 0; d < 3; ++d) f.ue[s][d] = fmaf(jm[s][d], cr, 0.5f * C.g[d]);
     }
@@ -102,7 +104,7 @@ __device__ __forceinline__ void vjp_forward(const float (&rho)[NS], const float 
         f.R += rho[s];
         f.n += rho[s] * C.invM[s];
     }
-    f.iR = 1.0f / f.R;
+    f.iR = rcp_nr(f.R);
 #pragma unroll
     for (int d = 0; d < 3; ++d) f.U[d] = 0.0f;
 #pragma unroll
@@ -275,15 +277,12 @@ __device__ __forceinline__ void vjp_finish(int s, const float (&rho)[NS], const 
     using L = Lat<LAT>;
     float dj[3];
     float drho = A.drho[s];
+    const float irho = f.live[s] ? rcp_nr(rho[s]) : 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         dg[d] += 0.5f * A.due[s][d];
-        if (f.live[s]) {
-            dj[d] = A.due[s][d] / rho[s];
-            drho -= A.due[s][d] * (f.ue[s][d] - 0.5f * C.g[d]) / rho[s];
-        } else {
-            dj[d] = 0.0f;
-        }
+        dj[d] = A.due[s][d] * irho;
+        drho -= A.due[s][d] * (f.ue[s][d] - 0.5f * C.g[d]) * irho;
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a)

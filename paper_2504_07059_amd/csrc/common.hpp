@@ -50,6 +50,17 @@ struct Tile {
     int32_t pad[3];
 };
 
+// Shapes of the species-split kernels: bx * by = 64 (one segment of 64
+// columns, any split of them), or W = bx * by / 64 segments of 64 columns
+// (bx a multiple of 64) with W <= 4 and ns * W <= 12 (the work-group must
+// fit one compute unit at three waves per SIMD).
+__host__ __device__ inline bool split_shape_ok(int bx, int by, int ns) {
+    if (bx < 1 || by < 1 || (bx * by) % 64) return false;
+    const int W = bx * by / 64;
+    if (W == 1) return true;
+    return bx % 64 == 0 && W <= 4 && ns * W <= 12;
+}
+
 // Launch description handed from the host library to the kernel launchers.
 struct Launch {
     const float* src;

@@ -1099,14 +1099,17 @@ lbm_mc_status lbm_mc_set_tuning(lbm_mc_ctx* c, int32_t bx, int32_t by, int32_t r
     if (rows) t.rows = rows;
     if (persistent >= 0) t.persistent = persistent;
     if (variant >= 0) t.split = variant;
-    else if (t.bx * t.by != 64) t.split = 0;   // keep the variant if the shape allows it
+    else if (!split_shape_ok(t.bx, t.by, c->N)) t.split = 0;   // keep it if the shape allows
     if (t.split != 0 && t.split != 1) return fail(LBM_MC_ERR_INVALID, "variant must be 0 or 1");
     if (t.bx < 8 || t.bx > 256 || t.bx % 8) return fail(LBM_MC_ERR_INVALID, "block_x must be 8..256, multiple of 8");
     if (c->DIM == 2 && t.by != 1) return fail(LBM_MC_ERR_INVALID, "block_y must be 1 in 2-D");
     if (t.by < 1 || t.bx * t.by > 256 || (t.bx * t.by) % 64)
         return fail(LBM_MC_ERR_INVALID, "block_x*block_y must be 64, 128, 192 or 256");
-    if (t.split && t.bx * t.by != 64)
-        return fail(LBM_MC_ERR_INVALID, "the species-split variant needs block_x*block_y = 64");
+    if (t.split && !split_shape_ok(t.bx, t.by, c->N))
+        return fail(LBM_MC_ERR_INVALID,
+                    "the species-split variant needs block_x*block_y = 64, or W = "
+                    "block_x*block_y/64 segments of 64 columns (block_x a multiple of 64) with "
+                    "N*W <= 12");
     if (t.split && c->hlp[0].eqb)
         return fail(LBM_MC_ERR_UNSUPPORTED,
                     "the equilibrium boundary runs execution variant 0 only");
@@ -1143,14 +1146,17 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
                     t.persistent = ps ? c->cus * (1024 / bx) : 0;
                     cands.push_back(t);
                 }
-        for (int r : rowsv)
-            for (int ps : {0, 1}) {
-                if (r > 2 * nm && r != 1) continue;
-                Tuning t;
-                t.bx = 64; t.by = 1; t.rows = r; t.split = 1;
-                t.persistent = ps ? c->cus * 8 : 0;
-                cands.push_back(t);
-            }
+        for (int bx : {64, 128, 192, 256})
+            for (int r : rowsv)
+                for (int ps : {0, 1}) {
+                    if (r > 2 * nm && r != 1) continue;
+                    if (!split_shape_ok(bx, 1, c->N)) continue;
+                    if (bx > 64 && ps) continue;
+                    Tuning t;
+                    t.bx = bx; t.by = 1; t.rows = r; t.split = 1;
+                    t.persistent = ps ? c->cus * 8 : 0;
+                    cands.push_back(t);
+                }
     } else {
         for (int bx : {32, 64, 128})
             for (int by : {1, 2, 4, 8})
@@ -1168,10 +1174,40 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
                 t.bx = bx; t.by = 64 / bx; t.rows = r; t.persistent = 0; t.split = 1;
                 cands.push_back(t);
             }
+        // several y rows of 64 columns per work-group
+        for (int by : {2, 3, 4})
+            for (int r : {8, 16, 32}) {
+                if (r > 2 * nm && r != 8) continue;
+                if (!split_shape_ok(64, by, c->N)) continue;
+                Tuning t;
+                t.bx = 64; t.by = by; t.rows = r; t.persistent = 0; t.split = 1;
+                cands.push_back(t);
+            }
     }
-    hipEvent_t e0, e1;
-    HIPCHECK(hipEventCreate(&e0));
-    HIPCHECK(hipEventCreate(&e1));
+    // the candidates write f~ into prev: from the first launch on it no
+    // longer holds f~(t-1), whatever happens below
+    c->prev_valid = false;
+    // on every exit: events destroyed, and (unless a best shape was
+    // installed) the shape in use before the call restored
+    struct Guard {
+        lbm_mc_ctx* c;
+        Tuning keep;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool done = false;
+        ~Guard() {
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+            if (!done) {
+                c->tune = keep;
+                const std::string msg = g_err;   // keep the failure's message
+                build_tiles(c);
+                g_err = msg;
+            }
+        }
+    } guard{c, c->tune};
+    HIPCHECK(hipEventCreate(&guard.e0));
+    HIPCHECK(hipEventCreate(&guard.e1));
+    hipEvent_t e0 = guard.e0, e1 = guard.e1;
     double best = 1e300;
     Tuning bestt = c->tune;
     for (const Tuning& t : cands) {
@@ -1201,18 +1237,15 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
             bestt = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     c->tune = bestt;
     lbm_mc_status st = build_tiles(c);
     if (st != LBM_MC_OK) return st;
+    guard.done = true;
     if (!c->hlp[0].eqb) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const auto& q = c->params[0];
         g_tune_cache[{c->lattice, c->N, q.nx, q.ny, q.nz, c->L, tune_kind(c)}] = bestt;
     }
-    // the candidates wrote f~ into prev: it no longer holds f~(t-1)
-    c->prev_valid = false;
     if (best_us) *best_us = best;
     return LBM_MC_OK;
 }

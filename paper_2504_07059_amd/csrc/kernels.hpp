@@ -663,6 +663,21 @@ __device__ __forceinline__ bool tile_column(const Tile& T, const LatParams& P, i
     return inside;
 }
 
+// tile_column for a work-group of W segments of 64 columns (W = bx by / 64):
+// with W = 1 the lanes are laid out as tile_column; with W > 1 (bx a multiple
+// of 64) segment seg is the 64 columns starting at x0 + 64 (seg mod (bx/64))
+// in row y0 + seg / (bx/64), lane = column.
+template <int LAT>
+__device__ __forceinline__ bool tile_column_seg(const Tile& T, const LatParams& P, int lane, int bx,
+                                                int seg, int W, int& x, int& y, bool& zero) {
+    if (W == 1) return tile_column<LAT>(T, P, lane, bx, x, y, zero);
+    const int per_row = bx >> 6;
+    Tile S = T;
+    S.x0 = T.x0 + 64 * (seg % per_row);
+    S.y0 = T.y0 + seg / per_row;
+    return tile_column<LAT>(S, P, lane, 64, x, y, zero);
+}
+
 #undef LBM_HP
 
 }  // namespace lbmmc

@@ -134,20 +134,30 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 
 // ------------------------------------------------------ species-split step
 // The same fused step with one wavefront per species: a work-group is NS
-// waves over the same 64 cross-section columns (bx * by = 64), wave s gathers
-// species s only, the waves exchange each node's (rho_s, u_s^eq) through LDS
+// waves over the same 64 cross-section columns, wave s gathers species s
+// only, the waves exchange each node's (rho_s, u_s^eq) through LDS
 // (double-buffered, one barrier per layer), and each wave then forms the
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, so several times more waves fit on a SIMD.
+//
+// A work-group may hold W such segments of 64 columns side by side
+// (threadIdx.z = segment; bx * by = 64 W): W consecutive 64-column pieces of
+// an x row in 2-D, W consecutive y rows of 64 columns in 3-D.  All NS x W
+// waves march the same layers in step (the per-layer barrier), so the
+// neighbour columns one segment reads at its edges (x halo in 2-D) or the
+// neighbour rows it reads across (y +- 1 in 3-D) are the rows its sibling
+// segments load in the same layer: they come from the caches instead of
+// memory, and only the work-group's outer halo is fetched twice.
 template <int LAT, int NS, int FRC, int EXT, int POL>
 struct SplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     Buf D;
     CollConst C;
     SpeciesConst K;
-    float4 (*xch)[NS][64];   // [2][NS][64] exchange buffers in LDS
-    float4 (*xgr)[NS][64];   // FRC 2: [2][NS][64] exchange of the density gradients
+    float4* xch;             // [2][W][NS][64] exchange buffers in LDS
+    float4* xgr;             // FRC 2: [2][W][NS][64] exchange of the density gradients
+    int xstride;             // W * NS * 64: floats4 per exchange buffer
     int s, lane;
     bool inside, bad;
     const float* dens;       // FRC 2: this species' density field
@@ -160,20 +170,21 @@ struct SplitOp {
         node_accel<LAT, EXT == 1>(accel, *P, C.g, dense_node<LAT>(*P, x, y, m), g);
         float rho_s, dlt_s, ue_s[3];
         species_moments<LAT>(P0, F, K.c, g, rho_s, dlt_s, ue_s);
-        float4 (*X)[64] = xch[m & 1];
-        X[s][lane] = make_float4(rho_s, ue_s[0], ue_s[1], ue_s[2]);
+        float4* X = xch + (m & 1) * xstride;
+        X[s * 64 + lane] = make_float4(rho_s, ue_s[0], ue_s[1], ue_s[2]);
         Grads gd{};
         if constexpr (FRC == 2) {
             const float* f = dens;
             field_grad<DIM>([&](int64_t j) { return f[j]; }, P->nx, P->ny, P->nz, P->wall_mask,
                             x, DIM == 2 ? m : y, DIM == 2 ? 0 : m, gd.gi);
-            xgr[m & 1][s][lane] = make_float4(gd.gi[0], gd.gi[1], gd.gi[2], 0.0f);
+            xgr[(m & 1) * xstride + s * 64 + lane] =
+                make_float4(gd.gi[0], gd.gi[1], gd.gi[2], 0.0f);
         }
         __syncthreads();
         if constexpr (FRC == 2) {
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
-                const float4 v = xgr[m & 1][j][lane];
+                const float4 v = xgr[(m & 1) * xstride + j * 64 + lane];
                 gd.gm[0] += v.x;
                 gd.gm[1] += v.y;
                 gd.gm[2] += v.z;
@@ -182,7 +193,7 @@ struct SplitOp {
         float rho[NS], ue[NS][3];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
-            const float4 v = X[j][lane];
+            const float4 v = X[j * 64 + lane];
             rho[j] = v.x;
             ue[j][0] = v.y;
             ue[j][1] = v.z;
@@ -224,20 +235,28 @@ struct SplitOp {
     }
 };
 
+// Work-group size limit of the species-split kernels: NS x W waves of 64
+// lanes with W <= 4 and NS x W <= 12 (three waves per SIMD).
+constexpr int kSplitMaxThreads = 768;
+
 template <int LAT, int NS, int FRC, int EXT, int POL>
-__global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ src,
-                                                    float* __restrict__ dst,
-                                                    const LatParams* __restrict__ lps,
-                                                    const Tile* __restrict__ tiles, int ntiles,
-                                                    int bx, const float* __restrict__ dens,
-                                                    const float* __restrict__ accel,
-                                                    unsigned* __restrict__ flag) {
+__global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
+        const float* __restrict__ src, float* __restrict__ dst,
+        const LatParams* __restrict__ lps, const Tile* __restrict__ tiles, int ntiles, int bx,
+        const float* __restrict__ dens, const float* __restrict__ accel,
+        unsigned* __restrict__ flag) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
-    __shared__ float4 xch[2][NS][64];
-    __shared__ float4 xgr[2][NS][FRC == 2 ? 64 : 1];
+    // [FRC == 2 ? 2 : 1][2][W][NS][64] float4: the exchange buffers (and those
+    // of the density gradients), sized by the launch
+    extern __shared__ float4 smem[];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int seg = __builtin_amdgcn_readfirstlane((int)threadIdx.z);
+    const int W = (int)blockDim.z;
+    const int xstride = W * NS * 64;
+    float4* xch = smem + seg * NS * 64;
+    float4* xgr = smem + 2 * xstride + seg * NS * 64;
     int t0, t1;
     tile_range(ntiles, t0, t1);
     bool bad = false;
@@ -248,7 +267,7 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         // barriers) and store nothing
         int x, y;
         bool zero;
-        const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
+        const bool inside = tile_column_seg<LAT>(T, P, lane, bx, seg, W, x, y, zero);
         const GatherConst G = gather_const(P, DIM);
         const int64_t lf = P.plane * NS * Q;
         // the species' own constants, read with the uniform species index
@@ -257,14 +276,13 @@ __global__ void __launch_bounds__(256) k_step_split(const float* __restrict__ sr
         SplitOp<LAT, NS, FRC, EXT, POL> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
                                               P.kdiff[s], P.cs2[s]},
-                                 xch, reinterpret_cast<float4 (*)[NS][64]>(xgr), s, lane,
-                                 inside, false,
+                                 xch, xgr, xstride, s, lane, inside, false,
                                  FRC == 2 ? dens + P.field_base * NS
                                                 + s * ((int64_t)P.nx * P.ny * P.nz)
                                           : nullptr,
                                  &P, x, y, accel};
-        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
-                    T.m1, op);
+        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx % 64 == 0,
+                    T.m0, T.m1, op);
         bad = bad || op.bad;
         __syncthreads();   // the next tile reuses the exchange buffers
     }
@@ -335,17 +353,18 @@ __global__ void __launch_bounds__(256) k_density(const float* __restrict__ src,
     }
 }
 
-// species-split form: block (64, NS), wave s streams species s
+// species-split form: block (64, NS, W), wave (s, seg) streams species s on
+// segment seg of the tile
 template <int LAT, int NS>
-__global__ void __launch_bounds__(256) k_density_split(const float* __restrict__ src,
-                                                       const LatParams* __restrict__ lps,
-                                                       const Tile* __restrict__ tiles,
-                                                       int ntiles, int bx,
-                                                       float* __restrict__ dens) {
+__global__ void __launch_bounds__(kSplitMaxThreads) k_density_split(
+        const float* __restrict__ src, const LatParams* __restrict__ lps,
+        const Tile* __restrict__ tiles, int ntiles, int bx, float* __restrict__ dens) {
     constexpr int DIM = Lat<LAT>::DIM;
     constexpr int Q = Lat<LAT>::Q;
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int seg = __builtin_amdgcn_readfirstlane((int)threadIdx.z);
+    const int W = (int)blockDim.z;
     int t0, t1;
     tile_range(ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
@@ -353,13 +372,13 @@ __global__ void __launch_bounds__(256) k_density_split(const float* __restrict__
         const LatParams& P = lps[T.lat];
         int x, y;
         bool zero;
-        const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
+        const bool inside = tile_column_seg<LAT>(T, P, lane, bx, seg, W, x, y, zero);
         const GatherConst G = gather_const(P, DIM);
         const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
         DensOp1<LAT> op{dens + P.field_base * NS + s * nodes, &P, x, y, inside};
         march1<LAT>(make_buf(src + P.base, P.plane * NS * Q, P.plane), G, s, L, x, y, zero,
-                    bx == 64, T.m0, T.m1, op);
+                    bx % 64 == 0, T.m0, T.m1, op);
     }
 }
 
@@ -615,7 +634,7 @@ static hipError_t by_shape(int ns, int frc, int ext, Fn&& fn) {
 
 template <int LAT_>
 hipError_t launch_step_lat(int ns, const Launch& L) {
-    if (L.split && L.bx * L.by != 64) return hipErrorInvalidValue;
+    if (L.split && !split_shape_ok(L.bx, L.by, ns)) return hipErrorInvalidValue;
     return by_shape<LAT_>(ns, L.forcing, L.eqb ? 3 : (L.accel ? 1 : (L.moving ? 2 : 0)),
                     [&](auto lat, auto n, auto frc, auto ex) -> hipError_t {
         constexpr int LAT = decltype(lat)::value, NS = decltype(n)::value,
@@ -626,9 +645,11 @@ hipError_t launch_step_lat(int ns, const Launch& L) {
             constexpr int POL = decltype(pol)::value;
             if constexpr (EXT != 3) {   // (the equilibrium boundary has no split form)
                 if (L.split) {
+                    const int W = L.bx * L.by / 64;
+                    const size_t lds = (FRC == 2 ? 2 : 1) * 2 * (size_t)W * NS * 64 * sizeof(float4);
                     hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, POL>), dim3(L.grid),
-                                       dim3(64, NS), 0, L.stream, L.src, L.dst, L.lp, L.tiles,
-                                       L.ntiles, L.bx, L.dens, L.accel, L.flag);
+                                       dim3(64, NS, W), lds, L.stream, L.src, L.dst, L.lp,
+                                       L.tiles, L.ntiles, L.bx, L.dens, L.accel, L.flag);
                     return hipGetLastError();
                 }
             }
@@ -651,8 +672,9 @@ hipError_t launch_step_lat(int ns, const Launch& L) {
                 if (!L.dens) return hipErrorInvalidValue;
                 // (the force does not enter the densities)
                 if (L.split)
-                    hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid), dim3(64, NS), 0,
-                                       L.stream, L.src, L.lp, L.tiles, L.ntiles, L.bx, L.dens);
+                    hipLaunchKernelGGL((k_density_split<LAT, NS>), dim3(L.grid),
+                                       dim3(64, NS, L.bx * L.by / 64), 0, L.stream, L.src, L.lp,
+                                       L.tiles, L.ntiles, L.bx, L.dens);
                 else
                     hipLaunchKernelGGL((k_density<LAT, NS>), dim3(L.grid), dim3(L.bx, L.by), 0,
                                        L.stream, L.src, L.lp, L.tiles, L.ntiles, L.dens);

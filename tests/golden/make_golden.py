@@ -117,6 +117,40 @@ def batched_sample():
     return {"workload": "batched_512_ternary_tubes", "steps": 10000, "tubes": out}
 
 
+LAYER_SEAMS = [(64, 0, 0), (63, 127, 127), (128, 50, 16), (127, 51, 15), (192, 100, 96),
+               (191, 101, 95), (0, 64, 112), (255, 65, 111), (64, 127, 32), (128, 0, 127)]
+
+
+def layer_crops_16():
+    """The 256x128x128 D3Q19 layer workload after 16 steps at ten nodes on the
+    seams of the library's default tiles (x = 63|64, 127|128, 191|192, 255|0;
+    z = 15|16, 31|32, 95|96, 111|112; every y row) and on both z walls: the
+    post-collision populations f~ and the mole fractions there, from the
+    oracle run on a crop of radius 17 around each node (after s steps a node
+    depends only on its radius-s neighbourhood; the crop wraps periodically in
+    x and y and keeps the z walls it reaches, so its centre is exact)."""
+    w = W.layer_mixing_3d()
+    x0 = w.x0()
+    steps, R = 16, 17
+    out = []
+    t0 = time.time()
+    for (x, y, z) in LAYER_SEAMS:
+        xs = [(x + k) % w.nx for k in range(-R, R + 1)]
+        ys = [(y + k) % w.ny for k in range(-R, R + 1)]
+        z0, z1 = max(0, z - R), min(w.nz, z + R + 1)
+        sub = np.ascontiguousarray(x0[:, z0:z1][:, :, ys][:, :, :, xs])
+        m = evd.Model("D3Q19", len(xs), len(ys), z1 - z0, w.masses,
+                      torch.tensor(w.diff, dtype=DTYPE), w.tau1, g=w.g,
+                      walls=(False, False, z0 == 0 or z1 == w.nz), n0=w.n0)
+        with torch.no_grad():
+            f = evd.run(m, evd.initial_populations(m, torch.tensor(sub, dtype=DTYPE)), steps)
+        ft = evd.collide(m, f)[:, :, z - z0, R, R]
+        xo = evd.observables(m, f)["x"][:, z - z0, R, R]
+        out.append({"node": [x, y, z], "f_post": ft.tolist(), "x": xo.tolist()})
+        print(f"  node {(x, y, z)} ({time.time() - t0:.0f} s)", flush=True)
+    return {"workload": w.name, "steps": steps, "radius": R, "nodes": out}
+
+
 HYPS = dict(nx=64, g=1e-5, x_mean=(0.4005, 0.249, 0.3505), steps=120000)
 
 
@@ -189,7 +223,7 @@ def adjoint_tube():
 JOBS = {"ternary_gravity": ternary_gravity, "binary_erf": binary_erf,
         "adjoint_tube": adjoint_tube, "layer_mixing_3d_small": layer_mixing_3d_small,
         "layer_mixing_3d_64": layer_mixing_3d_64, "hypsometric_walls": hypsometric_walls,
-        "batched_sample": batched_sample}
+        "batched_sample": batched_sample, "layer_crops_16": layer_crops_16}
 
 
 def main(names):

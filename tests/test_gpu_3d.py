@@ -137,3 +137,66 @@ def test_layer_full_size_5000_steps_properties():
     prof = x.double().mean(dim=(2, 3)).cpu().numpy()          # [N, nz]
     assert prof[3, -1] > prof[3, 0]
     sim.close()
+
+
+def test_layer_full_size_tile_seams_after_16_steps():
+    """256x128x128 at the library's default execution shape (64-column rows,
+    16-layer tiles), 16 steps: the post-collision populations and mole
+    fractions of ten nodes on the tile seams (x = 63|64, 127|128, 191|192,
+    255|0; z = 15|16, 31|32, 95|96, 111|112; every y row is a seam) and on both
+    z walls, against the stored oracle crops of radius 17
+    (tests/golden/layer_crops_16.json)."""
+    with open(os.path.join(GOLDEN, "layer_crops_16.json")) as fh:
+        G = json.load(fh)
+    w = W.layer_mixing_3d()
+    _announce(f"{w.name} tile seams, {G['steps']} steps")
+    lbm = _lbm()
+    sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+    assert sim.get_tuning()[:3] == (64, 1, 16)
+    sim.step(G["steps"])
+    raw = sim.raw("cur")
+    out = sim.moments()
+    x = sim.field(out, "x")
+    sim.sync()
+    wts = torch.tensor([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=DTYPE)
+    for rec in G["nodes"]:
+        cx, cy, cz = rec["node"]
+        s = raw[:, :, cz, cy, cx].double().cpu()
+        pop = (wts / wts[0])[None, :] * s[:, :1] + s
+        pop[:, 0] = s[:, 0]
+        ref = torch.tensor(rec["f_post"], dtype=DTYPE)
+        err = ((pop - ref).abs().max() / ref.abs().max()).item()
+        assert err < F_RTOL, (rec["node"], err)
+        dx = (x[:, cz, cy, cx].double().cpu() - torch.tensor(rec["x"], dtype=DTYPE)).abs().max()
+        assert dx.item() < X_TOL, (rec["node"], dx.item())
+    sim.close()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "layer_mixing_3d_64x32x32.npz")),
+                    reason="stored oracle field not generated (tests/golden/make_golden.py "
+                           "layer_mixing_3d_64)")
+def test_layer_64x32x32_5000_steps_whole_field():
+    """A 64x32x32 sub-problem of the layer workload (interface at z = 24),
+    whole mole-fraction field against the stored oracle at 100, 1000 and
+    5000 steps (tests/golden/layer_mixing_3d_64x32x32.npz), at the library's
+    default shape and at a shape with several tiles along every axis; FP64
+    mass against the oracle's."""
+    G = np.load(os.path.join(GOLDEN, "layer_mixing_3d_64x32x32.npz"))
+    w = W.layer_mixing_3d(64, 32, 32, steps=5000)
+    lbm = _lbm()
+    for tuning in (None, dict(block_x=32, block_y=2, rows=8)):
+        _announce(f"{w.name} whole field, tuning {tuning}")
+        sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        if tuning:
+            sim.set_tuning(**tuning)
+        t = 0
+        for cp in (100, 1000, 5000):
+            sim.step(cp - t)
+            t = cp
+            out = sim.moments()
+            sim.sync()
+            x = sim.field(out, "x").double().cpu().numpy()
+            dx = np.abs(x - G[f"x_{cp}"].astype(np.float64)).max()
+            assert dx < X_TOL, (tuning, cp, dx)
+            assert np.abs(out["mass"][0] / G[f"mass_{cp}"] - 1).max() < MASS_TOL
+        sim.close()
