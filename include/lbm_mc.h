@@ -24,7 +24,9 @@
  * library borrows them for the lifetime of a context and never frees them.
  * Their layout, per lattice, is [species][direction][z][y][x] with the x rows
  * padded to a pitch of a multiple of 32 floats; lbm_mc_layout() gives the
- * sizes and offsets.  Several lattices (the batched form) are concatenated in
+ * sizes and offsets.  The Q planes of one species must stay below 2 GiB
+ * (pitch * ny * nz * Q * 4 bytes; larger lattices are LBM_MC_ERR_UNSUPPORTED),
+ * so a buffer holds up to 8 GiB per lattice with 4 species.  Several lattices (the batched form) are concatenated in
  * one buffer.  Populations are stored post-collision: after lbm_mc_init the
  * "current" buffer holds the state s(0) of f~(0), after t steps s(t) of f~(t).
  * The state s of a population set f~ (per species and node) is

@@ -61,8 +61,8 @@ struct AdjSplitOp {
     static constexpr int Q = Lat<LAT>::Q;
     static constexpr int NG = NS * (NS - 1) / 2 + 3;
     static constexpr int KX = 4 + 5 * NS;   // packed contribution floats per species
-    Buf lam;      // lam_s(t), representation space
-    Buf mu;       // scratch, population space
+    Buf lam;      // lam_s(t), representation space (this species' view)
+    Buf mu;       // scratch, population space (this species' view)
     CollConst C;
     float (*x1)[4][64];
     float (*x2)[KX][64];
@@ -87,10 +87,10 @@ struct AdjSplitOp {
         x1[s][3][lane] = jz;
         // lam_f = T^T lam_s: lam_f0 = lam_P0 - sum_a (w_a/w_0) lam_ga, lam_fa = lam_ga
         float lt[Q];
-        float l0 = ldb(lam, s * Q, own);
+        float l0 = ldb(lam, 0, own);
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
-            lt[a] = ldb(lam, s * Q + a, own);
+            lt[a] = ldb(lam, a, own);
             l0 = fmaf(-L::wr(a), lt[a], l0);
         }
         lt[0] = l0;
@@ -161,7 +161,7 @@ struct AdjSplitOp {
         }
         if (inside) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) stb<POL>(mu, s * Q + a, own, lt[a]);
+            for (int a = 0; a < Q; ++a) stb<POL>(mu, a, own, lt[a]);
             int k = 0;
             // every wave holds the same dL/dK: the species-0 wave adds it
 #pragma unroll
@@ -193,14 +193,13 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
     int x, y;
     bool zero;
     const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
-    const int64_t lf = P.plane * NS * Q;
-    Op op{make_buf(lam + P.base, lf, P.plane), make_buf(mu + P.base, lf, P.plane),
+    Op op{species_buf<LAT>(lam + P.base, P.plane, s), species_buf<LAT>(mu + P.base, P.plane, s),
           coll_const(P), x1, x2, s, lane, inside, {}};
 #pragma unroll
     for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-    march1<LAT>(make_buf(fprev + P.base, lf, P.plane), G, s, L, x, y, zero, bx == 64, T.m0,
+    march1<LAT>(species_buf<LAT>(fprev + P.base, P.plane, s), G, s, L, x, y, zero, bx == 64, T.m0,
                 T.m1, op);
     block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
@@ -239,7 +238,7 @@ __device__ __forceinline__ void adj_stream_column(const Buf& M, const Buf& O,
     constexpr int Q = La::Q;
     constexpr int DIM = La::DIM;
     const Col& col = g.col;
-    const int pb0 = s * Q;
+    const int pb0 = 0;   // M and O are the species' views
     float acc0[Q], acc1[Q];
     if (s > 0) {
         const unsigned cm_ = layer_off(g, nbr(m0, -1, G.nm, g.wm)), c0_ = layer_off(g, m0);
@@ -354,9 +353,8 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
     const GatherConst G = gather_const(P, DIM);
     ColGeom g = col_geom<LAT>(G, x, y);
     if (zero) g.colbase += kSolid;
-    const int64_t lf = P.plane * NS * Q;
-    const Buf M = make_buf(mu + P.base, lf, P.plane);
-    const Buf O = make_buf(lamout + P.base, lf, P.plane);
+    const Buf M = species_buf<LAT>(mu + P.base, P.plane, s);
+    const Buf O = species_buf<LAT>(lamout + P.base, P.plane, s);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
     if (bx == 64) {
         const NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
@@ -380,7 +378,9 @@ __global__ void __launch_bounds__(256) k_adj_init(const LatParams* __restrict__ 
     const LatParams& P = lps[0];
     const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
     const CollConst C = coll_const(P);
-    const Buf Lb = make_buf(lam + P.base, P.plane * NS * Q, P.plane);
+    Buf Lb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Lb[s] = species_buf<LAT>(lam + P.base, P.plane, s);
     double acc[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) acc[q] = 0.0;
@@ -405,10 +405,10 @@ __global__ void __launch_bounds__(256) k_adj_init(const LatParams* __restrict__ 
                 jm[s][1] += (float)L::cy(a) * fa;
                 jm[s][2] += (float)L::cz(a) * fa;
             }
-            float l0 = ldb(Lb, s * Q, own);
+            float l0 = ldb(Lb[s], 0, own);
 #pragma unroll
             for (int a = 1; a < Q; ++a) {
-                lt[s][a] = ldb(Lb, s * Q + a, own);
+                lt[s][a] = ldb(Lb[s], a, own);
                 l0 = fmaf(-L::wr(a), lt[s][a], l0);
             }
             lt[s][0] = l0;

@@ -69,13 +69,13 @@ lbm_mc_status validate_params(const lbm_mc_params* p, int32_t L) {
         if (q.lattice == LBM_MC_D2Q9 && q.nz != 1)
             return fail(LBM_MC_ERR_INVALID, "lattice %d: D2Q9 needs nz = 1", l);
         {
+            // the kernels address each species' Q planes with 32-bit offsets
             const int64_t pitch = (q.nx + 31) / 32 * 32;
-            const int64_t floats = pitch * q.ny * q.nz * (int64_t)q.n_species *
-                                   (q.lattice == LBM_MC_D2Q9 ? 9 : 19);
+            const int64_t floats = pitch * q.ny * q.nz * (int64_t)(q.lattice == LBM_MC_D2Q9 ? 9 : 19);
             if (floats * 4 >= ((int64_t)1 << 31))
                 return fail(LBM_MC_ERR_UNSUPPORTED,
-                            "lattice %d: one lattice's populations exceed 2 GiB per buffer "
-                            "(%lld floats); split it or use fewer species", l, (long long)floats);
+                            "lattice %d: one species' populations exceed 2 GiB per buffer "
+                            "(%lld floats); split the lattice", l, (long long)floats);
         }
         int walls = 0, eq_walls = 0;
         for (int a = 0; a < 3; ++a) {

@@ -28,9 +28,10 @@
 // exact one-node shift.
 //
 // Addressing.  Loads and stores are buffer instructions: one buffer resource
-// per lattice and buffer (scalar registers), the plane as a scalar byte
-// offset and the node as a 32-bit per-lane byte offset, so no per-load 64-bit
-// address arithmetic is needed (a lattice holds at most 4 GB per buffer).
+// per species of a lattice (scalar registers), the direction plane as a
+// scalar byte offset and the node as a 32-bit per-lane byte offset, so no
+// per-load 64-bit address arithmetic is needed (each species' Q planes stay
+// below 2 GiB; a buffer holds up to 4 of them).
 //
 // For every node the gather hands over, per species s:
 //   P0[s]     the stored rest population at the node (it does not stream),
@@ -45,7 +46,8 @@
 
 namespace lbmmc {
 
-// Buffer view of one lattice's population buffer.
+// Buffer view of the Q planes of one species of a lattice (plane a of the view
+// is direction a of that species).
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
     int pb;   // bytes per plane
@@ -59,8 +61,15 @@ __device__ __forceinline__ Buf make_buf(const float* base, int64_t floats, int64
     return b;
 }
 
-// Byte offset that lies beyond any lattice buffer (the host keeps every
-// lattice below 2 GiB): a raw buffer load at it is range-checked and returns
+// The view of species s of a lattice whose planes start at `lattice`.
+template <int LAT>
+__device__ __forceinline__ Buf species_buf(const float* lattice, int64_t plane, int s) {
+    constexpr int Q = Lat<LAT>::Q;
+    return make_buf(lattice + (int64_t)s * Q * plane, (int64_t)Q * plane, plane);
+}
+
+// Byte offset that lies beyond any species view (the host keeps every
+// species below 2 GiB): a raw buffer load at it is range-checked and returns
 // 0, which is exactly the contribution of a solid (beyond-the-wall) source.
 constexpr unsigned kSolid = 0x80000000u;
 
@@ -567,30 +576,31 @@ __device__ __forceinline__ Sides wall_sides(const GatherConst& G, const ColGeom&
     return r;
 }
 
-// Forward pull gather of one column through layers [m0, m1), all species;
-// calls op(P0, F, m, own) for every layer m (own: byte offset of the node).
+// Forward pull gather of one column through layers [m0, m1), all species
+// (B: the species views); calls op(P0, F, m, own) for every layer m (own:
+// byte offset of the node within a plane).
 template <int LAT, int NS, bool EQ = false, class Op>
-__device__ __forceinline__ void march(const Buf& B, const GatherConst& G, int x, int y, int m0,
-                                      int m1, Op& op) {
+__device__ __forceinline__ void march(const Buf (&B)[NS], const GatherConst& G, int x, int y,
+                                      int m0, int m1, Op& op) {
     constexpr int Q = Lat<LAT>::Q;
     const ColGeom g = col_geom<LAT>(G, x, y);
     const NbLoad nb{};
     Heavy<LAT> h[NS > 1 ? NS - 1 : 1];
 #pragma unroll
-    for (int s = 1; s < NS; ++s) heavy_begin<LAT>(B, G, g, s * Q, G.lam[s], m0, h[s - 1], nb);
+    for (int s = 1; s < NS; ++s) heavy_begin<LAT>(B[s], G, g, 0, G.lam[s], m0, h[s - 1], nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
         const unsigned nxt = layer_off(g, mp);
         const Sides sd = wall_sides<LAT>(G, g, m);
         float P0[NS], F[NS][Q];
-        shift_layer<LAT, EQ>(B, G, g, m, own, P0[0], F[0]);
+        shift_layer<LAT, EQ>(B[0], G, g, m, own, P0[0], F[0]);
         if constexpr (EQ) {
-            if (sd.any) eq_wall_terms<LAT>(B, G, g, 0, G.lam[0], own, m, sd, F[0]);
+            if (sd.any) eq_wall_terms<LAT>(B[0], G, g, 0, G.lam[0], own, m, sd, F[0]);
         }
 #pragma unroll
         for (int s = 1; s < NS; ++s)
-            heavy_layer<LAT, EQ>(B, G, g, s * Q, G.lam[s], own, nxt, m, sd, h[s - 1], P0[s], F[s],
+            heavy_layer<LAT, EQ>(B[s], G, g, 0, G.lam[s], own, nxt, m, sd, h[s - 1], P0[s], F[s],
                                  nb);
         op(P0, F, m, own);
     }
@@ -602,7 +612,7 @@ __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, in
                                           Op& op, const NB& nb) {
     constexpr int Q = Lat<LAT>::Q;
     Heavy<LAT> h;
-    if (s > 0) heavy_begin<LAT>(B, G, g, s * Q, L, m0, h, nb);
+    if (s > 0) heavy_begin<LAT>(B, G, g, 0, L, m0, h, nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
@@ -611,14 +621,14 @@ __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, in
         if (s == 0)
             shift_layer<LAT>(B, G, g, m, own, P0, F);
         else
-            heavy_layer<LAT>(B, G, g, s * Q, L, own, nxt, m, wall_sides<LAT>(G, g, m), h, P0, F,
+            heavy_layer<LAT>(B, G, g, 0, L, own, nxt, m, wall_sides<LAT>(G, g, m), h, P0, F,
                              nb);
         op(P0, F, m, own);
     }
 }
 
-// The same gather for one species s (uniform over the wave) with weight
-// triple L; calls op(P0, F, m, own) with the species' values.  With wave_row
+// The same gather for one species s (uniform over the wave; B its view) with
+// weight triple L; calls op(P0, F, m, own) with the species' values.  With wave_row
 // the wave's 64 lanes are 64 consecutive columns of one row (in order) and the
 // x neighbours are taken across lanes.  lane_zero marks a lane whose reads
 // all return 0.

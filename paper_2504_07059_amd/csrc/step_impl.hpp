@@ -78,7 +78,7 @@ __device__ __forceinline__ void species_grads(const float* dens, const LatParams
 template <int LAT, int NS, int FRC, int EXT, int POL>
 struct StepOp {
     static constexpr int Q = Lat<LAT>::Q;
-    Buf D;
+    Buf D[NS];               // the destination's species views
     CollConst C;
     bool bad;
     const float* dens;      // FRC 2: this lattice's density fields
@@ -97,9 +97,9 @@ struct StepOp {
         if (!collide<LAT, NS, FRC>(P0, F, C, g, gi, mw, W)) bad = true;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            stb<POL>(D, s * Q, own, P0[s]);
+            stb<POL>(D[s], 0, own, P0[s]);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) stb<POL>(D, s * Q + a, own, F[s][a]);
+            for (int a = 1; a < Q; ++a) stb<POL>(D[s], a, own, F[s][a]);
         }
     }
 };
@@ -122,11 +122,16 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
         const int y = DIM == 3 ? T.y0 + (int)threadIdx.y : 0;
         if (x >= P.nx || (DIM == 3 && y >= P.ny)) continue;
         const GatherConst G = gather_const(P, DIM);
-        const int64_t lf = P.plane * NS * Lat<LAT>::Q;
-        StepOp<LAT, NS, FRC, EXT, POL> op{make_buf(dst + P.base, lf, P.plane), coll_const(P), false,
+        StepOp<LAT, NS, FRC, EXT, POL> op{{}, coll_const(P), false,
                                     FRC == 2 ? dens + P.field_base * NS : nullptr, &P, x, y,
                                     accel};
-        march<LAT, NS, EXT == 3>(make_buf(src + P.base, lf, P.plane), G, x, y, T.m0, T.m1, op);
+        Buf B[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            B[s] = species_buf<LAT>(src + P.base, P.plane, s);
+            op.D[s] = species_buf<LAT>(dst + P.base, P.plane, s);
+        }
+        march<LAT, NS, EXT == 3>(B, G, x, y, T.m0, T.m1, op);
         bad = bad || op.bad;
     }
     if (bad) atomicOr(flag, 1u);
@@ -227,9 +232,9 @@ struct SplitOp {
         const bool ok = collide_species<LAT, FRC>(K, g, rho_s, dlt_s, ue_s, M, V, gd, P0, F) &&
                         isfinite(M.R);
         if (inside) {
-            stb<POL>(D, s * Q, own, P0);
+            stb<POL>(D, 0, own, P0);
 #pragma unroll
-            for (int a = 1; a < Q; ++a) stb<POL>(D, s * Q + a, own, F[a]);
+            for (int a = 1; a < Q; ++a) stb<POL>(D, a, own, F[a]);
             bad = bad || !ok;
         }
     }
@@ -269,11 +274,11 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
         bool zero;
         const bool inside = tile_column_seg<LAT>(T, P, lane, bx, seg, W, x, y, zero);
         const GatherConst G = gather_const(P, DIM);
-        const int64_t lf = P.plane * NS * Q;
         // the species' own constants, read with the uniform species index
         // (scalar loads; no run-time indexing of register arrays)
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-        SplitOp<LAT, NS, FRC, EXT, POL> op{make_buf(dst + P.base, lf, P.plane), coll_const(P),
+        SplitOp<LAT, NS, FRC, EXT, POL> op{species_buf<LAT>(dst + P.base, P.plane, s),
+                                 coll_const(P),
                                  SpeciesConst{P.c[s], P.inv_cs2[s], P.inv_tau[s], P.fpref[s],
                                               P.kdiff[s], P.cs2[s]},
                                  xch, xgr, xstride, s, lane, inside, false,
@@ -281,8 +286,8 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
                                                 + s * ((int64_t)P.nx * P.ny * P.nz)
                                           : nullptr,
                                  &P, x, y, accel};
-        march1<LAT>(make_buf(src + P.base, lf, P.plane), G, s, L, x, y, zero, bx % 64 == 0,
-                    T.m0, T.m1, op);
+        march1<LAT>(species_buf<LAT>(src + P.base, P.plane, s), G, s, L, x, y, zero,
+                    bx % 64 == 0, T.m0, T.m1, op);
         bad = bad || op.bad;
         __syncthreads();   // the next tile reuses the exchange buffers
     }
@@ -348,7 +353,10 @@ __global__ void __launch_bounds__(256) k_density(const float* __restrict__ src,
         const GatherConst G = gather_const(P, DIM);
         const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
         DensOp<LAT, NS> op{dens + P.field_base * NS, &P, nodes, x, y};
-        march<LAT, NS>(make_buf(src + P.base, P.plane * NS * Lat<LAT>::Q, P.plane), G, x, y,
+        Buf B[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) B[s] = species_buf<LAT>(src + P.base, P.plane, s);
+        march<LAT, NS>(B, G, x, y,
                        T.m0, T.m1, op);
     }
 }
@@ -377,7 +385,7 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_density_split(
         const int64_t nodes = (int64_t)P.nx * P.ny * P.nz;
         const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
         DensOp1<LAT> op{dens + P.field_base * NS + s * nodes, &P, x, y, inside};
-        march1<LAT>(make_buf(src + P.base, P.plane * NS * Q, P.plane), G, s, L, x, y, zero,
+        march1<LAT>(species_buf<LAT>(src + P.base, P.plane, s), G, s, L, x, y, zero,
                     bx % 64 == 0, T.m0, T.m1, op);
     }
 }
@@ -582,7 +590,9 @@ __global__ void __launch_bounds__(256) k_moments(const float* __restrict__ src,
             }
         } else {
             const GatherConst G = gather_const(P, DIM);
-            const Buf B = make_buf(lb, P.plane * NS * Q, P.plane);
+            Buf B[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) B[s] = species_buf<LAT>(lb, P.plane, s);
             march<LAT, NS, EQ>(B, G, x, y, T.m0, T.m1, op);
         }
     }

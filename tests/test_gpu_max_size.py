@@ -1,13 +1,14 @@
-"""The largest lattices the library accepts: a D2Q9 box of 32768 x 450 nodes
-with 4 species, walls on x and y (edges and corners), 2.12 GB per population
-buffer, and a D3Q19 box of 256 x 128 x 215 nodes with 4 species closed on all
-three axes, 2.14 GB per buffer: just under the 2 GiB per-buffer limit.  The last planes then sit at
-byte offsets near 2^31, where the solid-source markers and the buffer range
-checks of the gather are at their limits.  Sampled nodes after two steps
-against the oracle on crops (exact at their centres: influence spreads one
-node per step), including the four corners and nodes of the last species;
-one more row is rejected before any device work.  Bar: populations within
-2e-6 of the largest (FP32 rounding of two steps)."""
+"""The largest lattices the library accepts: each species' Q planes just
+under 2 GiB, four species to a buffer of 8.6 GB.  A D2Q9 box of 32768 x 1820
+nodes with walls on x and y (edges and corners), and a D3Q19 box of
+256 x 128 x 862 nodes closed on all three axes.  The last species' planes
+then start beyond 6 GiB in the buffer and their own last planes sit at byte
+offsets near 2^31 within the species, where the solid-source markers and the
+buffer range checks of the gather are at their limits.  Sampled nodes after
+two steps against the oracle on crops (exact at their centres: influence
+spreads one node per step), including the four corners and nodes of the last
+species; one more row is rejected before any device work.  Bar: populations
+within 2e-6 of the largest (FP32 rounding of two steps)."""
 import numpy as np
 import pytest
 import torch
@@ -18,7 +19,8 @@ from oracle.lattice import DTYPE
 
 F_RTOL = 2e-6
 STEPS = 2
-NX, NY = 32768, 450
+NX, NY = 32768, 1820
+NZ3 = 862
 MASSES = [1.0, 2.0, 3.0, 4.0]
 
 
@@ -37,7 +39,7 @@ def _workload(ny=NY):
 
 def test_one_row_more_is_rejected_before_device_work():
     lbm = _lbm()
-    w = _workload(NY + 6)
+    w = _workload(NY + 1)
     st, _, msg = lbm.check_problem(lbm.params_from_workload(w), np.full((4, 1, 1, 1), 0.25))
     assert st == 2 and "2 GiB" in msg, msg
 
@@ -50,7 +52,9 @@ def test_largest_lattice_sampled_nodes_match_oracle_crops(shape):
     print(f"\n[gpu case] max-size box {NX}x{NY}, 4 species, shape {shape}", flush=True)
     x0 = w.x0()
     total, _, pitch, _ = lbm.layout(lbm.params_from_workload(w))
-    assert total * 4 < 2 ** 31 and total * 4 > 2 ** 31 - 2 ** 26
+    species_bytes = pitch[0] * NY * 9 * 4
+    assert species_bytes < 2 ** 31 and species_bytes > 2 ** 31 - 2 ** 26
+    assert total * 4 > 4 * (2 ** 31 - 2 ** 26)   # four species of nearly 2 GiB: 8.6 GB
     sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
     if shape:
         sim.set_tuning(*shape)
@@ -85,7 +89,7 @@ def _workload_3d():
     rng = np.random.default_rng(22)
     d = rng.uniform(0.06, 0.1, size=(4, 4))
     diff = ((d + d.T) / 2).tolist()
-    return W.Workload("max_box_3d", "D3Q19", 256, 128, 215, MASSES, diff, 1.0,
+    return W.Workload("max_box_3d", "D3Q19", 256, 128, NZ3, MASSES, diff, 1.0,
                       [1e-5, 0.0, -1e-5], [True, True, True], STEPS, "random", seed=22)
 
 
@@ -93,16 +97,19 @@ def _workload_3d():
 def test_largest_3d_lattice_sampled_nodes_match_oracle_crops():
     lbm = _lbm()
     w = _workload_3d()
-    print("\n[gpu case] max-size 3-D box 256x128x215, 4 species", flush=True)
+    print(f"\n[gpu case] max-size 3-D box 256x128x{NZ3}, 4 species", flush=True)
     x0 = w.x0()
     total, _, _, _ = lbm.layout(lbm.params_from_workload(w))
-    assert total * 4 < 2 ** 31 and total * 4 > 2 ** 31 - 2 ** 26
+    species_bytes = 256 * 128 * NZ3 * 19 * 4
+    assert species_bytes < 2 ** 31 and species_bytes > 2 ** 31 - 2 ** 26
+    assert total * 4 > 4 * (2 ** 31 - 2 ** 26)   # four species of nearly 2 GiB: 8.6 GB
     sim = lbm.LbmMc(lbm.params_from_workload(w), x0)
     sim.step(STEPS)
     raw = sim.raw("cur")
     dims = (w.nx, w.ny, w.nz)
-    pts = [(0, 0, 0), (255, 127, 214), (0, 127, 214), (255, 0, 0), (128, 0, 107),
-           (0, 64, 214), (255, 127, 0), (77, 33, 150), (1, 126, 213)]
+    L = NZ3 - 1
+    pts = [(0, 0, 0), (255, 127, L), (0, 127, L), (255, 0, 0), (128, 0, NZ3 // 2),
+           (0, 64, L), (255, 127, 0), (77, 33, 600), (1, 126, L - 1)]
     got = torch.stack([raw[:, :, z, y, x] for (x, y, z) in pts]).double().cpu()   # [P, N, Q]
     sim.sync()
     sim.close()
