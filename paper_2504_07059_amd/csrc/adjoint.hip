@@ -182,7 +182,6 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
                                                      const Tile* __restrict__ tiles, int bx,
                                                      double* __restrict__ gpart) {
     constexpr int DIM = Lat<LAT>::DIM;
-    constexpr int Q = Lat<LAT>::Q;
     using Op = AdjSplitOp<LAT, NS, POL>;
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
@@ -340,7 +339,6 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
                                                     const LatParams* __restrict__ lps,
                                                     const Tile* __restrict__ tiles, int bx) {
     constexpr int DIM = Lat<LAT>::DIM;
-    constexpr int Q = Lat<LAT>::Q;
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const Tile T = tiles[blockIdx.x];

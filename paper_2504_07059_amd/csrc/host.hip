@@ -455,10 +455,10 @@ int tune_kind(const lbm_mc_ctx* c) {
 void drop_graphs(lbm_mc_ctx* c) {
     for (auto& row : c->gexec)
         for (auto& g : row) {
-            if (g) hipGraphExecDestroy(g);
+            if (g) (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
-    for (auto& g : c->seq_graphs) hipGraphExecDestroy(g.exec);
+    for (auto& g : c->seq_graphs) (void)hipGraphExecDestroy(g.exec);
     c->seq_graphs.clear();
 }
 
@@ -474,7 +474,7 @@ lbm_mc_status run_sequence(lbm_mc_ctx* c, int kind, const void* a, const void* b
             return LBM_MC_OK;
         }
     if (c->seq_graphs.size() >= 8) {
-        for (auto& g : c->seq_graphs) hipGraphExecDestroy(g.exec);
+        for (auto& g : c->seq_graphs) (void)hipGraphExecDestroy(g.exec);
         c->seq_graphs.clear();
     }
     HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -482,13 +482,13 @@ lbm_mc_status run_sequence(lbm_mc_ctx* c, int kind, const void* a, const void* b
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap, &graph);
     if (st != LBM_MC_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return st;
     }
     if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
     c->seq_graphs.push_back({kind, a, b, d, n, stride, exec});
     HIPCHECK(hipGraphLaunch(exec, c->stream));
@@ -520,14 +520,14 @@ lbm_mc_status build_tiles(lbm_mc_ctx* c) {
     }
     const size_t nt = c->htiles.size();
     if (nt > c->dtiles_cap) {
-        if (c->dtiles) hipFree(c->dtiles);
+        if (c->dtiles) (void)hipFree(c->dtiles);
         c->dtiles = nullptr;
         HIPCHECK(hipMalloc(&c->dtiles, nt * sizeof(Tile)));
         c->dtiles_cap = nt;
     }
     const size_t np = nt * (size_t)(c->N + 3);
     if (np > c->dpartial_cap) {
-        if (c->dpartial) hipFree(c->dpartial);
+        if (c->dpartial) (void)hipFree(c->dpartial);
         c->dpartial = nullptr;
         HIPCHECK(hipMalloc(&c->dpartial, np * sizeof(double)));
         c->dpartial_cap = np;
@@ -640,12 +640,12 @@ lbm_mc_status get_graph(lbm_mc_ctx* c, int cls, hipGraphExec_t* out) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (st != LBM_MC_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st;
         }
         if (e != hipSuccess) return fail(LBM_MC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&c->gexec[cls][key], g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess)
             return fail(LBM_MC_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
     }
@@ -721,7 +721,7 @@ lbm_mc_status adjoint_prepare(lbm_mc_ctx* c) {
     const size_t ng = (size_t)(c->N * (c->N - 1) / 2 + 3);
     const size_t need = ng * std::max((size_t)c->adj_ntiles, (size_t)init_blocks(c));
     if (need > c->dgpart_cap) {
-        if (c->dgpart) hipFree(c->dgpart);
+        if (c->dgpart) (void)hipFree(c->dgpart);
         c->dgpart = nullptr;
         HIPCHECK(hipMalloc(&c->dgpart, need * sizeof(double)));
         c->dgpart_cap = need;
@@ -880,7 +880,7 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
     };
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "no HIP device"));
-    hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (profile_scratch(&c->static_scratch) != hipSuccess)
         return bail(fail(LBM_MC_ERR_HIP, "device address of the profile scratch"));
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
@@ -972,7 +972,7 @@ static lbm_mc_status init_impl(const lbm_mc_params* p, int32_t n_lattices, const
     if (n_lattices == 1)
         c->dx0 = dx0;
     else
-        hipFree(dx0);
+        (void)hipFree(dx0);
     if (e != hipSuccess) return bail(fail(LBM_MC_ERR_HIP, "init: %s", hipGetErrorString(e)));
     c->prev_valid = true;
     c->t = 0;
@@ -1195,8 +1195,8 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool done = false;
         ~Guard() {
-            if (e0) hipEventDestroy(e0);
-            if (e1) hipEventDestroy(e1);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
             if (!done) {
                 c->tune = keep;
                 const std::string msg = g_err;   // keep the failure's message
@@ -1259,21 +1259,21 @@ lbm_mc_status lbm_mc_set_batched_mode(lbm_mc_ctx* c, int32_t one_launch) {
 
 lbm_mc_status lbm_mc_destroy(lbm_mc_ctx* c) {
     if (!c) return LBM_MC_OK;
-    if (c->stream || c->dlp) hipStreamSynchronize(c->stream);
+    if (c->stream || c->dlp) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    if (c->cap) hipStreamDestroy(c->cap);
-    hipFree(c->dlp);
-    hipFree(c->dflag);
-    hipFree(c->dtiles);
-    hipFree(c->dpartial);
-    hipFree(c->dtotals);
-    hipFree(c->dens);
-    hipFree(c->dmu);
-    hipFree(c->dgpart);
-    hipFree(c->dlam);
-    hipFree(c->dx0);
-    hipFree(c->adj_tiles);
-    hipFree(c->dprof);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    (void)hipFree(c->dlp);
+    (void)hipFree(c->dflag);
+    (void)hipFree(c->dtiles);
+    (void)hipFree(c->dpartial);
+    (void)hipFree(c->dtotals);
+    (void)hipFree(c->dens);
+    (void)hipFree(c->dmu);
+    (void)hipFree(c->dgpart);
+    (void)hipFree(c->dlam);
+    (void)hipFree(c->dx0);
+    (void)hipFree(c->adj_tiles);
+    (void)hipFree(c->dprof);
     delete c;
     return LBM_MC_OK;
 }
@@ -1312,7 +1312,7 @@ lbm_mc_status lbm_mc_profile(lbm_mc_ctx* c, const float* state, double* xbar) {
     profile_chunks(c, rows_per, nchunks);
     const size_t need = (size_t)nchunks * c->N * c->params[0].nx;
     if (need > c->dprof_cap) {
-        if (c->dprof) hipFree(c->dprof);
+        if (c->dprof) (void)hipFree(c->dprof);
         c->dprof = nullptr;
         c->dprof_cap = 0;
         HIPCHECK(hipMalloc(&c->dprof, need * sizeof(double)));
