@@ -82,7 +82,8 @@ def _timed_steps(sim, steps, warmup):
 
 
 # ------------------------------------------------------------------ roofline
-KERNEL_SOURCES = ("step_impl.hpp", "kernels.hpp", "collide.hpp", "lattice.hpp", "common.hpp")
+KERNEL_SOURCES = ("step_impl.hpp", "kernels.hpp", "collide.hpp", "lattice.hpp", "common.hpp",
+                  "host.hip")
 
 
 def kernel_sources_sha():

@@ -505,9 +505,14 @@ lbm_mc_status build_tiles(lbm_mc_ctx* c) {
         const int nyb = c->DIM == 3 ? (q.ny + T.by - 1) / T.by : 1;
         const int nmc = (nm + T.rows - 1) / T.rows;
         c->hlp[l].tile_begin = (int)c->htiles.size();
-        for (int xb = 0; xb < nxb; ++xb)
+        // layer ranges outermost: the tiles side by side in the cross-section
+        // are consecutive in the list, so they run at the same time on one
+        // XCD and the x halo one tile reads is the line its neighbour reads in
+        // the same layer (2-D: 4 % faster on the 16384x1024 tube, 1 % on the
+        // batch; neutral in 3-D)
+        for (int mc = 0; mc < nmc; ++mc)
             for (int yb = 0; yb < nyb; ++yb)
-                for (int mc = 0; mc < nmc; ++mc) {
+                for (int xb = 0; xb < nxb; ++xb) {
                     Tile t{};
                     t.lat = l;
                     t.x0 = xb * T.bx;
@@ -1135,7 +1140,7 @@ lbm_mc_status lbm_mc_autotune(lbm_mc_ctx* c, int32_t reps, double* best_us) {
     std::vector<Tuning> cands;
     int nm = 0;
     for (const auto& q : c->params) nm = std::max(nm, c->DIM == 2 ? q.ny : q.nz);
-    const int rowsv[] = {1, 2, 4, 8, 16, 32, 64, 128};
+    const int rowsv[] = {1, 2, 4, 8, 12, 16, 24, 32, 64, 128};
     if (c->DIM == 2) {
         for (int bx : {64, 128, 256})
             for (int r : rowsv)
