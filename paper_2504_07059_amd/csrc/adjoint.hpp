@@ -166,38 +166,103 @@ __device__ __forceinline__ void vjp_species(int i, const float (&rho)[NS], const
     const float* U = f.U;
     const float uD = U[0] * du[0] + U[1] * du[1] + U[2] * du[2];
     const float uV = U[0] * V[0] + U[1] * V[1] + U[2] * V[2];
-    float gU[3] = {0, 0, 0}, gdu[3] = {0, 0, 0}, gV[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
-    float s_uD = 0.0f, s_uV = 0.0f, s_uF = 0.0f, s_UU = 0.0f, drf = 0.0f;
+    // Every per-direction term of the reverse sweep is lam_a w_a times a
+    // polynomial of degree <= 3 in e_a = c (cx, cy, cz): the sweep reduces
+    // to the moments of w_a lam_a over the directions.  With integer
+    // components in {-1, 0, 1}: n0 = sum w lam, n1_j = sum w lam e_j,
+    // n2_jk = sum w lam e_j e_k, n3_jk = sum w lam e_j^2 e_k (j != k); the
+    // third moments with three distinct axes vanish on both lattices and
+    // e_j^3 = e_j, so the e-moments are c n1, c^2 n2 and c^3 n3 (n1 on the
+    // diagonal).  Then, with P_a = beta + ics e.U + ics^2 (e.U)^2 / 2,
+    // beta = 1 - ics U.U / 2 and dfeq_a = lam_a (alpha + ics e.Z),
+    // alpha = itau (1 - ics u.D) + ics u.V, Z = itau D - V:
+    //   PM0 = sum w lam P,  PM1 = sum w lam P e,
+    //   drho_i += alpha PM0 + ics Z.PM1, and the vector sums below.
+    constexpr int D = L::DIM;
+    auto ec = [](int a, int j) { return j == 0 ? L::cx(a) : (j == 1 ? L::cy(a) : L::cz(a)); };
+    float n0 = 0.0f, n1[3] = {0.0f, 0.0f, 0.0f}, n2[3][3] = {}, n3[3][3] = {};
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        const float ex = c * L::cx(a), ey = c * L::cy(a), ez = c * L::cz(a);
-        const float w = L::w(a);
-        const float eU = ex * U[0] + ey * U[1] + ez * U[2];
-        const float eD = ex * du[0] + ey * du[1] + ez * du[2];
-        const float eV = ex * V[0] + ey * V[1] + ez * V[2];
-        const float eF = ex * Fv[0] + ey * Fv[1] + ez * Fv[2];
-        const float P = 1.0f + ics * eU + 0.5f * ics * ics * eU * eU - 0.5f * ics * f.UU;
-        const float feq = w * rho[i] * P;
         const float lam = lt[a];
         lt[a] = (1.0f - itau) * lam;
-        const float df0 = itau * lam;
-        const float dfeq = df0 * (1.0f + ics * (eD - uD)) - lam * ics * (eV - uV);
-        const float deD = df0 * feq * ics;
-        const float deV = -lam * feq * ics;
-        const float dS = fp * lam;
-        const float deF = dS * w * ics * (1.0f + ics * eU);
-        float deU = dS * w * ics * ics * eF;
-        drf += dfeq * w * P;
-        const float dP = dfeq * w * rho[i];
-        deU += dP * (ics + ics * ics * eU);
-        s_UU += -0.5f * ics * dP;
-        s_uD -= deD;
-        s_uV -= deV;
-        s_uF -= dS * w * ics;
-        gU[0] += deU * ex; gU[1] += deU * ey; gU[2] += deU * ez;
-        gdu[0] += deD * ex; gdu[1] += deD * ey; gdu[2] += deD * ez;
-        gV[0] += deV * ex; gV[1] += deV * ey; gV[2] += deV * ez;
-        gF[0] += deF * ex; gF[1] += deF * ey; gF[2] += deF * ez;
+        const float wl = L::w(a) * lam;
+        n0 += wl;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (ec(a, j) == 0) continue;
+            n1[j] += ec(a, j) > 0 ? wl : -wl;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                if (k == j || ec(a, k) == 0) continue;
+                n3[j][k] += ec(a, k) > 0 ? wl : -wl;
+                if (k > j) n2[j][k] += ec(a, j) * ec(a, k) > 0 ? wl : -wl;
+            }
+            n2[j][j] += wl;
+        }
+    }
+    const float c2 = c * c, c3 = c2 * c;
+    float M1[3], M2U[3], M2Z[3], M2F[3], M3UU[3], M3ZU[3], Z[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Z[j] = fmaf(itau, du[j], -V[j]);
+        M1[j] = M2U[j] = M2Z[j] = M2F[j] = M3UU[j] = M3ZU[j] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        M1[j] = c * n1[j];
+        float u2 = 0.0f, z2 = 0.0f, f2 = 0.0f, uu = n1[j] * U[j] * U[j],
+              zu = n1[j] * Z[j] * U[j];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float m = k == j ? n2[j][j] : (k > j ? n2[j][k] : n2[k][j]);
+            u2 = fmaf(m, U[k], u2);
+            z2 = fmaf(m, Z[k], z2);
+            f2 = fmaf(m, Fv[k], f2);
+            if (k == j) continue;
+            // M3_jjk and M3_kkj terms
+            uu = fmaf(2.0f * n3[j][k], U[j] * U[k], uu);
+            uu = fmaf(n3[k][j], U[k] * U[k], uu);
+            zu = fmaf(n3[j][k], fmaf(Z[j], U[k], Z[k] * U[j]), zu);
+            zu = fmaf(n3[k][j], Z[k] * U[k], zu);
+        }
+        M2U[j] = c2 * u2;
+        M2Z[j] = c2 * z2;
+        M2F[j] = c2 * f2;
+        M3UU[j] = c3 * uu;
+        M3ZU[j] = c3 * zu;
+    }
+    const float beta = fmaf(-0.5f * ics, f.UU, 1.0f);
+    const float alpha = fmaf(itau, fmaf(-ics, uD, 1.0f), ics * uV);
+    float UM1 = 0.0f, ZM1 = 0.0f, UM2U = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        UM1 = fmaf(U[j], M1[j], UM1);
+        ZM1 = fmaf(Z[j], M1[j], ZM1);
+        UM2U = fmaf(U[j], M2U[j], UM2U);
+    }
+    const float hics2 = 0.5f * ics * ics;
+    const float PM0 = fmaf(hics2, UM2U, fmaf(ics, UM1, beta * n0));
+    float PM1[3] = {0.0f, 0.0f, 0.0f}, ZPM1 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        PM1[j] = fmaf(hics2, M3UU[j], fmaf(ics, M2U[j], beta * M1[j]));
+        ZPM1 = fmaf(Z[j], PM1[j], ZPM1);
+    }
+    const float ri = rho[i];
+    const float drf = fmaf(ics, ZPM1, alpha * PM0);
+    const float s_UU = -0.5f * ics * ri * fmaf(ics, ZM1, alpha * n0);
+    const float s_uD = -itau * ics * ri * PM0;
+    const float s_uV = ics * ri * PM0;
+    const float s_uF = -fp * ics * n0;
+    float gU[3], gdu[3], gV[3], gF[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float a1 = fmaf(ics, M2U[j], M1[j]);
+        const float a2 = fmaf(ics, M3ZU[j], M2Z[j]);
+        gU[j] = fmaf(fp * ics * ics, M2F[j], ri * ics * fmaf(alpha, a1, ics * a2));
+        gdu[j] = itau * ics * ri * PM1[j];
+        gV[j] = -ics * ri * PM1[j];
+        gF[j] = fp * ics * a1;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
