@@ -351,6 +351,7 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
     diffusivities and g through the checkpointed adjoint: time per forward +
     backward step against a plain forward step on the same lattice, and the
     reverse step alone."""
+    import dataclasses
     import torch
     import lbm_workloads as W
     from paper_2504_07059_amd import adjoint as A
@@ -386,6 +387,7 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
     torch.cuda.synchronize()
     replay_us = e0.elapsed_time(e1) * 1e3 / (K - 1)
     reverse_us = e2.elapsed_time(e3) * 1e3 / K
+    sim_total = sim.total
     sim.close()
     del seg
     out = {"workload": f"adjoint_tube_{nx}x{ny}", "steps": steps, "checkpoint_every": K,
@@ -397,6 +399,11 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
            "fwd_bwd_roofline": roofline(None, 252 * species_nodes,
                                         (fwd_us + replay_us + reverse_us) * 1e-3, 1)}
     out["fwd_bwd_kernel_over_forward"] = out["fwd_bwd_kernel_us_per_step"] / fwd_us
+    # every state recorded in the forward (checkpoint_every = 0, memory
+    # permitting): the forward is the recording replay, nothing is recomputed
+    out["recorded_fwd_bwd_kernel_us_per_step"] = replay_us + reverse_us
+    out["recorded_fwd_bwd_kernel_over_forward"] = (replay_us + reverse_us) / fwd_us
+    out["recorded_state_bytes"] = 4 * sim_total * (steps + 1)
     if not fwd_bwd:
         return out
     with torch.no_grad():
@@ -420,6 +427,18 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
                 "fwd_bwd_first_call_ms_per_step": wall_cold * 1e3 / steps,
                 "loss": L.item(), "grad_pairs": p_t.grad.tolist(),
                 "grad_g": g_t.grad.tolist()})
+    # the same gradient with every state recorded in the forward
+    prob_k, prob = prob, dataclasses.replace(prob, checkpoint_every=0)
+    run()
+    wall_r, L_r, p_r, g_r = run()
+    prob = prob_k
+    out.update({"recorded_fwd_bwd_wall_ms_per_step": wall_r * 1e3 / steps,
+                "recorded_fwd_bwd_wall_over_forward": wall_r * 1e6 / steps / fwd_us,
+                "recorded_loss_equals_checkpointed": L_r.item() == L.item(),
+                "recorded_grad_max_rel_diff": max(
+                    abs(u - v) / max(abs(v), 1e-300)
+                    for u, v in zip(p_r.grad.tolist() + g_r.grad.tolist()[:1],
+                                    p_t.grad.tolist() + g_t.grad.tolist()[:1]))})
     gpath = os.path.join(GOLDEN, "adjoint_tube.json")
     if (nx, ny, steps, K) == (512, 64, 4000, 100) and os.path.exists(gpath):
         G = json.load(open(gpath))

@@ -24,7 +24,10 @@ from . import lbm
 class Problem:
     """Everything but the differentiated parameters: geometry, masses, tau_1,
     walls, initial mole fractions [N, nz, ny, nx], number of steps and the
-    checkpoint interval."""
+    checkpoint interval.  checkpoint_every = K >= 1 keeps every K-th state
+    and recomputes each segment in the backward; checkpoint_every = 0 records
+    every state in the forward (steps + 1 states of the population layout in
+    device memory) and recomputes nothing."""
     lattice: str
     nx: int
     ny: int
@@ -79,8 +82,24 @@ class Evolve(torch.autograd.Function):
         gv = [float(v) for v in g.detach().cpu().tolist()]
         sim = _sim(problem, pv, gv)
         K = int(problem.checkpoint_every)
-        if K < 1:
-            raise ValueError("checkpoint_every must be >= 1")
+        if K < 0:
+            raise ValueError("checkpoint_every must be >= 0")
+        ctx.pairs_meta = (pairs.device, pairs.dtype)
+        ctx.g_meta = (g.device, g.dtype)
+        ctx.sim, ctx.problem = sim, problem
+        if K == 0:
+            # every state, s(0) .. s(T), one row each: the forward itself
+            # writes them (lbm_mc_replay), the backward reads them
+            stride = (sim.total + 63) // 64 * 64
+            states = torch.empty((problem.steps + 1, stride), dtype=torch.float32,
+                                 device=sim.device)
+            states[0, : sim.total].copy_(sim.buffers()[0])
+            if problem.steps > 0:
+                sim.replay(states[0], problem.steps, states[1:])
+            ctx.states, ctx.ckpts = states, None
+            ctx.s_T = states[problem.steps, : sim.total]
+            return sim.profile(ctx.s_T)
+        ctx.states = None
         ckpts = {}
         t = 0
         while t < problem.steps:
@@ -90,9 +109,7 @@ class Evolve(torch.autograd.Function):
             t += n
         s_T = sim.buffers()[0].clone()
         xbar = sim.profile(s_T)
-        ctx.sim, ctx.ckpts, ctx.problem, ctx.s_T = sim, ckpts, problem, s_T
-        ctx.pairs_meta = (pairs.device, pairs.dtype)
-        ctx.g_meta = (g.device, g.dtype)
+        ctx.ckpts, ctx.s_T = ckpts, s_T
         return xbar
 
     @staticmethod
@@ -104,18 +121,24 @@ class Evolve(torch.autograd.Function):
         sim.profile_vjp(ctx.s_T, dxbar, lam_a)
         grad = torch.zeros(problem.n_pairs + 3, dtype=torch.float64, device=dev)
         K = int(problem.checkpoint_every)
-        stride = (sim.total + 63) // 64 * 64
-        seg = torch.empty((min(K, problem.steps), stride), dtype=torch.float32, device=dev)
-        for t0 in sorted(ctx.ckpts, reverse=True):
-            n = min(K, problem.steps - t0)
-            seg[0, : sim.total].copy_(ctx.ckpts[t0])
-            if n > 1:
-                sim.replay(seg[0], n - 1, seg[1:n])
-            sim.adjoint_run(seg, n, lam_a, lam_b, grad)
-            lam_a, lam_b = lam_b, lam_a
+        if K == 0:
+            if problem.steps > 0:
+                sim.adjoint_run(ctx.states, problem.steps, lam_a, lam_b, grad)
+                lam_a, lam_b = lam_b, lam_a
+        else:
+            stride = (sim.total + 63) // 64 * 64
+            seg = torch.empty((min(K, problem.steps), stride), dtype=torch.float32, device=dev)
+            for t0 in sorted(ctx.ckpts, reverse=True):
+                n = min(K, problem.steps - t0)
+                seg[0, : sim.total].copy_(ctx.ckpts[t0])
+                if n > 1:
+                    sim.replay(seg[0], n - 1, seg[1:n])
+                sim.adjoint_run(seg, n, lam_a, lam_b, grad)
+                lam_a, lam_b = lam_b, lam_a
         sim.adjoint_init(lam_a, grad)
         ctx.sim = None
         ctx.ckpts = None
+        ctx.states = None
         ctx.s_T = None
         npair = problem.n_pairs
         return (grad[:npair].to(*ctx.pairs_meta), grad[npair:].to(*ctx.g_meta), None)

@@ -462,12 +462,18 @@ void drop_graphs(lbm_mc_ctx* c) {
     c->seq_graphs.clear();
 }
 
+// Sequences longer than this are enqueued directly: a graph of thousands of
+// launches (a whole recorded trajectory) is rarely replayed with the same
+// buffers, and capturing and instantiating it costs more than the launches.
+constexpr int64_t kMaxGraphSequence = 512;
+
 // Run a launch sequence through a captured graph, capturing it on first use
 // for this argument set (at most 8 kept).  issue(stream) enqueues the
 // kernels; it must not record memsets.
 template <class Issue>
 lbm_mc_status run_sequence(lbm_mc_ctx* c, int kind, const void* a, const void* b, const void* d,
                            int64_t n, int64_t stride, Issue&& issue) {
+    if (n > kMaxGraphSequence) return issue(c->stream);
     for (auto& g : c->seq_graphs)
         if (g.kind == kind && g.a == a && g.b == b && g.c == d && g.n == n && g.stride == stride) {
             HIPCHECK(hipGraphLaunch(g.exec, c->stream));

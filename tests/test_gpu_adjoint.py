@@ -292,6 +292,26 @@ def test_misfit_gradient_small_tube_matches_oracle():
     assert abs(dg[1]) <= 1e-6 * abs(dg_ref[0]) and dg[2] == 0.0
 
 
+def test_recorded_states_give_the_checkpointed_gradient():
+    """checkpoint_every = 0 records every state in the forward and recomputes
+    nothing; the reverse steps then run on the same states as with
+    checkpoints (the recomputation is bitwise the forward step): the loss is
+    identical, and the gradient too up to the grouping of its FP64 sums (per
+    segment with checkpoints, once over the run when recorded), also for a
+    run of one step."""
+    import dataclasses
+    for steps in (400, 1):
+        _announce(f"recorded states 96x4, {steps} steps")
+        truth, ev, prob = _tube_problem(96, 4, steps, 64)
+        target = np.full((ev.n_species, 96), 1.0 / ev.n_species)
+        L_ref, dp_ref, dg_ref = _gpu_gradient(ev, prob, target)
+        L, dp, dg = _gpu_gradient(ev, dataclasses.replace(prob, checkpoint_every=0), target)
+        assert L == L_ref
+        scale = max(abs(v) for v in dp_ref + dg_ref)
+        for u, v in zip(dp + dg, dp_ref + dg_ref):
+            assert abs(u - v) <= 1e-12 * scale, (u, v)
+
+
 def test_misfit_gradient_full_tube_matches_stored_oracle():
     """The full adjoint workload: 512x64 tube, 4000 steps, checkpoints every
     100 steps; gradient with respect to the three D_ij and g_x against the
