@@ -302,7 +302,9 @@ lbm_mc_status lbm_mc_adjoint_init(lbm_mc_ctx* ctx, const float* lam0, double* gr
  *     xbar_i(x) = (1/(ny nz)) sum over y, z of x_i(x, y, z),
  * x_i = rho_i/(M_i n), n = sum_j rho_j/M_j (Sec. 3), rho_i = P0/w_0 + sum g_a
  * of the state (the collision conserves rho_i, so this is the profile of the
- * observables at that step; Sec. 4.1 reports such region averages).
+ * observables at that step).  The region averages that Sec. 4.1 reports for
+ * the two halves of the tube are the means of xbar_i over x < nx/2 and over
+ * x >= nx/2 (regions of equal node counts).
  * Evaluated in FP64 with a fixed-order reduction (reproducible).
  *   state  device float, population layout (buffer_floats), e.g. a buffer of
  *          lbm_mc_state or a checkpoint; read only.
