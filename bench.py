@@ -22,7 +22,7 @@ The JSON line carries, besides the contract's keys:
                 `traffic` is the counted HBM bytes per launch (FETCH_SIZE +
                 WRITE_SIZE, copy-calibrated) from the committed profile of the
                 same kernel sources and shape, else null; `ceiling` is the
-                same rate against the streaming copy of this build
+                same rate against the library's streaming copy
                 (lbm_mc_stream_copy), the practical read-write ceiling.
   accuracy      the paired accuracy gate: the same batch run for its
                 configured 10,000 steps at the timed shape, sampled tubes
@@ -130,7 +130,7 @@ def roofline(name, per_launch_bytes, ms, steps, tuning=None, ceiling=None, bound
 
 # ------------------------------------------------------------ streaming copy
 def copy_sweep(sizes_gib=(1, 2, 4), blocks_per_cu=(1, 2, 4, 8), reps=5):
-    """The streaming copy of this build over buffer sizes and grid sizes: the
+    """The library's streaming copy over buffer sizes and grid sizes: the
     best read+write rate over buffers of 2 GiB and more (well beyond the
     256 MB last-level cache) is the practical ceiling of a read-one-write-one
     kernel."""
