@@ -27,7 +27,8 @@ class Problem:
     checkpoint interval.  checkpoint_every = K >= 1 keeps every K-th state
     and recomputes each segment in the backward; checkpoint_every = 0 records
     every state in the forward (steps + 1 states of the population layout in
-    device memory) and recomputes nothing."""
+    device memory) and recomputes nothing; None records every state when
+    they take at most half of the free device memory, else uses K = 100."""
     lattice: str
     nx: int
     ny: int
@@ -37,7 +38,7 @@ class Problem:
     walls: Sequence[bool]
     x0: np.ndarray
     steps: int
-    checkpoint_every: int = 100
+    checkpoint_every: Optional[int] = 100
     n0: float = 0.0
     tuning: Optional[dict] = None
     stats: dict = field(default_factory=dict)
@@ -72,6 +73,16 @@ def _sim(problem, pairs, g):
     return sim
 
 
+def _interval(problem, sim):
+    """The checkpoint interval to use (0: record every state)."""
+    if problem.checkpoint_every is not None:
+        return int(problem.checkpoint_every)
+    stride = (sim.total + 63) // 64 * 64
+    need = 4 * stride * (problem.steps + 1)
+    free, _ = torch.cuda.mem_get_info(sim.device)
+    return 0 if need <= free // 2 else 100
+
+
 class Evolve(torch.autograd.Function):
     """xbar(T): the profile of s(T) = Phi^T(s(0; D, g); D, g), s(0) the
     initialised state."""
@@ -81,9 +92,10 @@ class Evolve(torch.autograd.Function):
         pv = [float(v) for v in pairs.detach().cpu().tolist()]
         gv = [float(v) for v in g.detach().cpu().tolist()]
         sim = _sim(problem, pv, gv)
-        K = int(problem.checkpoint_every)
+        K = _interval(problem, sim)
         if K < 0:
             raise ValueError("checkpoint_every must be >= 0")
+        ctx.K = K
         ctx.pairs_meta = (pairs.device, pairs.dtype)
         ctx.g_meta = (g.device, g.dtype)
         ctx.sim, ctx.problem = sim, problem
@@ -120,7 +132,7 @@ class Evolve(torch.autograd.Function):
         lam_b = torch.zeros_like(lam_a)
         sim.profile_vjp(ctx.s_T, dxbar, lam_a)
         grad = torch.zeros(problem.n_pairs + 3, dtype=torch.float64, device=dev)
-        K = int(problem.checkpoint_every)
+        K = ctx.K
         if K == 0:
             if problem.steps > 0:
                 sim.adjoint_run(ctx.states, problem.steps, lam_a, lam_b, grad)

@@ -305,11 +305,14 @@ def test_recorded_states_give_the_checkpointed_gradient():
         truth, ev, prob = _tube_problem(96, 4, steps, 64)
         target = np.full((ev.n_species, 96), 1.0 / ev.n_species)
         L_ref, dp_ref, dg_ref = _gpu_gradient(ev, prob, target)
-        L, dp, dg = _gpu_gradient(ev, dataclasses.replace(prob, checkpoint_every=0), target)
-        assert L == L_ref
         scale = max(abs(v) for v in dp_ref + dg_ref)
-        for u, v in zip(dp + dg, dp_ref + dg_ref):
-            assert abs(u - v) <= 1e-12 * scale, (u, v)
+        # recorded explicitly, and by the automatic choice (a small problem
+        # fits in memory)
+        for K in (0, None):
+            L, dp, dg = _gpu_gradient(ev, dataclasses.replace(prob, checkpoint_every=K), target)
+            assert L == L_ref
+            for u, v in zip(dp + dg, dp_ref + dg_ref):
+                assert abs(u - v) <= 1e-12 * scale, (K, u, v)
 
 
 def test_misfit_gradient_full_tube_matches_stored_oracle():
