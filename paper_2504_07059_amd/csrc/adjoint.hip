@@ -69,7 +69,29 @@ struct AdjSplitOp {
     int s, lane;
     bool inside;
     double acc[NG];
+    // kernel A alone: lam_f = T^T lam_s(t) from the stored adjoint
     __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int, unsigned own) {
+        using L = Lat<LAT>;
+        // lam_f0 = lam_P0 - sum_a (w_a/w_0) lam_ga, lam_fa = lam_ga
+        float lt[Q];
+        float l0 = ldb(lam, 0, own);
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            lt[a] = ldb(lam, a, own);
+            l0 = fmaf(-L::wr(a), lt[a], l0);
+        }
+        lt[0] = l0;
+        reverse(P0, F, lt, own);
+    }
+    // fused reverse step: lam_f(t) given in population space (the transposed
+    // stream of the later step's mu, computed by the caller)
+    __device__ __forceinline__ void operator()(float P0, float (&F)[Q], float (&lt)[Q],
+                                               unsigned own) {
+        reverse(P0, F, lt, own);
+    }
+    // the collision VJP at f(t) = (P0, F) of lam_f = lt; lt becomes mu
+    __device__ __forceinline__ void reverse(float P0, float (&F)[Q], float (&lt)[Q],
+                                            unsigned own) {
         using L = Lat<LAT>;
         // own density and momentum (sum_a w_a = 1, sum_a c_a w_a = 0)
         float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
@@ -85,15 +107,6 @@ struct AdjSplitOp {
         x1[s][1][lane] = jx;
         x1[s][2][lane] = jy;
         x1[s][3][lane] = jz;
-        // lam_f = T^T lam_s: lam_f0 = lam_P0 - sum_a (w_a/w_0) lam_ga, lam_fa = lam_ga
-        float lt[Q];
-        float l0 = ldb(lam, 0, own);
-#pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            lt[a] = ldb(lam, a, own);
-            l0 = fmaf(-L::wr(a), lt[a], l0);
-        }
-        lt[0] = l0;
         __syncthreads();
         float rho[NS], jm[NS][3];
 #pragma unroll
@@ -227,107 +240,163 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
             : (Fr::p1(La::opp(a)) < 0) ? hpass<LAT, 0, -1>(M, pidx, CEN, col, L, nb)       \
                                        : hpass<LAT, 0, 0>(M, pidx, CEN, col, L, nb)))
 
-template <int LAT, int POL, class NB>
-__device__ __forceinline__ void adj_stream_column(const Buf& M, const Buf& O,
-                                                  const GatherConst& G, const ColGeom& g, int s,
-                                                  const float (&L)[3], int m0, int m1,
-                                                  bool inside, const NB& nb) {
+// Marching state of the reversed gather of one heavier species: the
+// marching-axis partial sums of its planes of mu.
+template <int LAT>
+struct RevMarch {
+    float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
+};
+
+// Start the reversed gather of species s (M: its view of mu) at layer m0.
+template <int LAT, class NB>
+__device__ __forceinline__ void rev_begin(const Buf& M, const GatherConst& G, const ColGeom& g,
+                                          int s, const float (&L)[3], int m0, RevMarch<LAT>& r,
+                                          const NB& nb) {
+    using Fr = Frame<LAT>;
+    using La = Lat<LAT>;
+    constexpr int Q = La::Q;
+    const Col& col = g.col;
+    if (s == 0) return;
+    const unsigned cm_ = layer_off(g, nbr(m0, -1, G.nm, g.wm)), c0_ = layer_off(g, m0);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        if (Fr::pm(a) != 0) {
+            const int pidx = a;
+            const W3 wmar = wsel(-Fr::pm(a), L);
+            const float hm = LBM_HPR(cm_);
+            const float h0 = LBM_HPR(c0_);
+            r.acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
+            r.acc1[a] = wmar.m * h0;
+        } else {
+            r.acc0[a] = 0.0f;
+            r.acc1[a] = 0.0f;
+        }
+    }
+}
+
+// lam_f(t-1) at layer m of the column (population space): the reversed
+// gather of mu plus the transposed wall terms.
+template <int LAT, class NB>
+__device__ __forceinline__ void rev_layer(const Buf& M, const GatherConst& G, const ColGeom& g,
+                                          int s, const float (&L)[3], int m, unsigned own,
+                                          unsigned nxt, RevMarch<LAT>& r,
+                                          float (&lf)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
     constexpr int Q = La::Q;
     constexpr int DIM = La::DIM;
     const Col& col = g.col;
-    const int pb0 = 0;   // M and O are the species' views
-    float acc0[Q], acc1[Q];
-    if (s > 0) {
-        const unsigned cm_ = layer_off(g, nbr(m0, -1, G.nm, g.wm)), c0_ = layer_off(g, m0);
+    lf[0] = ldb(M, 0, own);
+    if (s == 0) {
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
-            if (Fr::pm(a) != 0) {
-                const int pidx = pb0 + a;
-                const W3 wmar = wsel(-Fr::pm(a), L);
-                const float hm = LBM_HPR(cm_);
-                const float h0 = LBM_HPR(c0_);
-                acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
-                acc1[a] = wmar.m * h0;
-            } else {
-                acc0[a] = 0.0f;
-                acc1[a] = 0.0f;
+            // source X + c_a (the reversed shift); where it is solid, the
+            // bounce-back transpose mu_abar(X)
+            const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
+            unsigned src = own;
+            bool solid = false;
+            if (c0 > 0) { src += col.bxp; solid = solid || col.sxp; }
+            if (c0 < 0) { src += col.bxm; solid = solid || col.sxm; }
+            if constexpr (DIM == 3) {
+                if (c1 > 0) { src += col.byp; solid = solid || col.syp; }
+                if (c1 < 0) { src += col.bym; solid = solid || col.sym; }
             }
+            if (cm != 0) {
+                const int ms = nbr(m, cm, G.nm, g.wm);
+                solid = solid || ms < 0;
+                src += (unsigned)(ms - m) * g.lsb;
+            }
+            const int lo = a < La::opp(a) ? a : La::opp(a);
+            const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
+                                      : src + (unsigned)((a - lo) * M.pb);
+            lf[a] = ldb(M, lo, sg);
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        const int pidx = a;
+        if (Fr::pm(a) == 0) {
+            lf[a] = LBM_HPR(own);
+        } else {
+            const W3 wmar = wsel(-Fr::pm(a), L);
+            const float hn = LBM_HPR(nxt);   // 0 beyond a wall
+            lf[a] = fmaf(wmar.p, hn, r.acc0[a]);
+            r.acc0[a] = fmaf(wmar.z, hn, r.acc1[a]);
+            r.acc1[a] = wmar.m * hn;
         }
     }
+    // transposed wall terms (walls on one axis): the forward adds
+    // lambda_+1 f~_a(X) + lambda_-1 f~_abar(X) to f_a(X) for a pointing
+    // away from the wall
+    const Sides sd = wall_sides<LAT>(G, g, m);
+    if (sd.any) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            int away = 0, toward = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int p = sd.s[ax] * Fr::comp(a, ax);
+                away += p < 0;
+                toward += p > 0;
+            }
+            if (away) lf[a] = fmaf(L[2], ldb(M, a, own), lf[a]);
+            if (toward) lf[a] = fmaf(L[0], ldb(M, La::opp(a), own), lf[a]);
+        }
+    }
+}
+
+template <int LAT, int POL, class NB>
+__device__ __forceinline__ void adj_stream_column(const Buf& M, const Buf& O,
+                                                  const GatherConst& G, const ColGeom& g, int s,
+                                                  const float (&L)[3], int m0, int m1,
+                                                  bool inside, const NB& nb) {
+    using La = Lat<LAT>;
+    constexpr int Q = La::Q;
+    RevMarch<LAT> r;
+    rev_begin<LAT>(M, G, g, s, L, m0, r, nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
         const unsigned own = layer_off(g, m);
         const unsigned nxt = layer_off(g, mp);
         float lf[Q];
-        lf[0] = ldb(M, pb0, own);
-        if (s == 0) {
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                // source X + c_a (the reversed shift); where it is solid, the
-                // bounce-back transpose mu_abar(X)
-                const int c0 = Fr::p0(a), c1 = Fr::p1(a), cm = Fr::pm(a);
-                unsigned src = own;
-                bool solid = false;
-                if (c0 > 0) { src += col.bxp; solid = solid || col.sxp; }
-                if (c0 < 0) { src += col.bxm; solid = solid || col.sxm; }
-                if constexpr (DIM == 3) {
-                    if (c1 > 0) { src += col.byp; solid = solid || col.syp; }
-                    if (c1 < 0) { src += col.bym; solid = solid || col.sym; }
-                }
-                if (cm != 0) {
-                    const int ms = nbr(m, cm, G.nm, g.wm);
-                    solid = solid || ms < 0;
-                    src += (unsigned)(ms - m) * g.lsb;
-                }
-                const int lo = a < La::opp(a) ? a : La::opp(a);
-                const unsigned sg = solid ? own + (unsigned)((La::opp(a) - lo) * M.pb)
-                                          : src + (unsigned)((a - lo) * M.pb);
-                lf[a] = ldb(M, lo, sg);
-            }
-        } else {
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const int pidx = pb0 + a;
-                if (Fr::pm(a) == 0) {
-                    lf[a] = LBM_HPR(own);
-                } else {
-                    const W3 wmar = wsel(-Fr::pm(a), L);
-                    const float hn = LBM_HPR(nxt);   // 0 beyond a wall
-                    lf[a] = fmaf(wmar.p, hn, acc0[a]);
-                    acc0[a] = fmaf(wmar.z, hn, acc1[a]);
-                    acc1[a] = wmar.m * hn;
-                }
-            }
-            // transposed wall terms (walls on one axis): the forward adds
-            // lambda_+1 f~_a(X) + lambda_-1 f~_abar(X) to f_a(X) for a pointing
-            // away from the wall
-            const Sides sd = wall_sides<LAT>(G, g, m);
-            if (sd.any) {
-#pragma unroll
-                for (int a = 1; a < Q; ++a) {
-                    int away = 0, toward = 0;
-#pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        const int p = sd.s[ax] * Fr::comp(a, ax);
-                        away += p < 0;
-                        toward += p > 0;
-                    }
-                    if (away) lf[a] = fmaf(L[2], ldb(M, pb0 + a, own), lf[a]);
-                    if (toward) lf[a] = fmaf(L[0], ldb(M, pb0 + La::opp(a), own), lf[a]);
-                }
-            }
-        }
+        rev_layer<LAT>(M, G, g, s, L, m, own, nxt, r, lf, nb);
         if (inside) {
             float lp0 = lf[0];
 #pragma unroll
             for (int a = 1; a < Q; ++a) {
                 lp0 = fmaf(La::wr(a), lf[a], lp0);
-                stb<POL>(O, pb0 + a, own, lf[a]);
+                stb<POL>(O, a, own, lf[a]);
             }
-            stb<POL>(O, pb0, own, lp0);
+            stb<POL>(O, 0, own, lp0);
         }
+    }
+}
+
+// The fused reverse step's march over one column: per layer the forward
+// gather of f(t) from f~(t-1) (B: the species' view of the state) and the
+// reversed gather of the later step's mu (M), then op(P0, F, lam_f, own).
+template <int LAT, class NB, class Op>
+__device__ __forceinline__ void march_fused(const Buf& B, const Buf& M, const GatherConst& G,
+                                            int s, const float (&L)[3], const ColGeom& g, int m0,
+                                            int m1, Op& op, const NB& nb) {
+    constexpr int Q = Lat<LAT>::Q;
+    Heavy<LAT> h;
+    RevMarch<LAT> r;
+    if (s > 0) heavy_begin<LAT>(B, G, g, 0, L, m0, h, nb);
+    rev_begin<LAT>(M, G, g, s, L, m0, r, nb);
+    for (int m = m0; m < m1; ++m) {
+        const int mp = nbr(m, 1, G.nm, g.wm);
+        const unsigned own = layer_off(g, m);
+        const unsigned nxt = layer_off(g, mp);
+        float P0, F[Q], lf[Q];
+        if (s == 0)
+            shift_layer<LAT>(B, G, g, m, own, P0, F);
+        else
+            heavy_layer<LAT>(B, G, g, 0, L, own, nxt, m, wall_sides<LAT>(G, g, m), h, P0, F,
+                             nb);
+        rev_layer<LAT>(M, G, g, s, L, m, own, nxt, r, lf, nb);
+        op(P0, F, lf, own);
     }
 }
 
@@ -360,6 +429,50 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
     } else {
         adj_stream_column<LAT, POL>(M, O, G, g, s, L, T.m0, T.m1, inside, NbLoad{});
     }
+}
+
+// ------------------------------------------------------- fused reverse step
+// Kernel B of step t+1 and kernel A of step t in one pass: lam_f(t) = S^T
+// mu(t+1) is gathered from the later step's scratch mu (mu_in) where kernel A
+// would read lam_s(t); the adjoint stays in population space between the two,
+// so the storage transform and its inverse drop out, and mu(t) goes to mu_out.
+// The parameter gradients accumulate as in kernel A.
+template <int LAT, int NS, int POL>
+__global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fprev,
+                                                   const float* __restrict__ mu_in,
+                                                   float* __restrict__ mu_out,
+                                                   const LatParams* __restrict__ lps,
+                                                   const Tile* __restrict__ tiles, int bx,
+                                                   double* __restrict__ gpart) {
+    constexpr int DIM = Lat<LAT>::DIM;
+    using Op = AdjSplitOp<LAT, NS, POL>;
+    __shared__ float x1[NS][4][64];
+    __shared__ float x2[NS][Op::KX][64];
+    const int lane = (int)threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const Tile T = tiles[blockIdx.x];
+    const LatParams& P = lps[T.lat];
+    int x, y;
+    bool zero;
+    const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
+    const Buf M = species_buf<LAT>(mu_in + P.base, P.plane, s);
+    // (the op's stored-adjoint view is not read on this path)
+    Op op{M, species_buf<LAT>(mu_out + P.base, P.plane, s), coll_const(P), x1, x2, s, lane,
+          inside, {}};
+#pragma unroll
+    for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    const GatherConst G = gather_const(P, DIM);
+    const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
+    ColGeom g = col_geom<LAT>(G, x, y);
+    if (zero) g.colbase += kSolid;
+    const Buf B = species_buf<LAT>(fprev + P.base, P.plane, s);
+    if (bx == 64) {
+        const NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
+        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, nb);
+    } else {
+        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, NbLoad{});
+    }
+    block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
 // ----------------------------------------------------------------- init VJP
@@ -497,6 +610,33 @@ hipError_t launch_adjoint(int lattice, int ns, const Launch& L, const float* lam
         if (ns == 2) return adj_t<1, 2>(L, lam_in, mu, gpart);
         if (ns == 3) return adj_t<1, 3>(L, lam_in, mu, gpart);
         if (ns == 4) return adj_t<1, 4>(L, lam_in, mu, gpart);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int LAT, int NS>
+static hipError_t adjf_t(const Launch& L, const float* mu_in, float* mu_out, double* gpart) {
+    if (L.bx * L.by != 64) return hipErrorInvalidValue;
+    auto go = [&](auto pol) {
+        hipLaunchKernelGGL((k_adj_fused<LAT, NS, decltype(pol)::value>), dim3(L.ntiles),
+                           dim3(64, NS), 0, L.stream, L.src, mu_in, mu_out, L.lp, L.tiles, L.bx,
+                           gpart);
+    };
+    if (L.wt)
+        go(std::integral_constant<int, kStoreWT>{});
+    else
+        go(std::integral_constant<int, kStoreNT>{});
+    return hipGetLastError();
+}
+
+// D2Q9 only: with D3Q19's marching state the fused kernel would hold one wave
+// per SIMD for three or more species, where kernels A and B hold two and eight
+hipError_t launch_adjoint_fused(int lattice, int ns, const Launch& L, const float* mu_in,
+                                float* mu_out, double* gpart) {
+    if (lattice == 0) {
+        if (ns == 2) return adjf_t<0, 2>(L, mu_in, mu_out, gpart);
+        if (ns == 3) return adjf_t<0, 3>(L, mu_in, mu_out, gpart);
+        if (ns == 4) return adjf_t<0, 4>(L, mu_in, mu_out, gpart);
     }
     return hipErrorInvalidValue;
 }

@@ -101,6 +101,10 @@ hipError_t launch_adjoint(int lattice, int nspecies, const Launch& L, const floa
                           float* mu, double* gpart, int ng);
 hipError_t launch_adjoint_stream(int lattice, int nspecies, const Launch& L, const float* mu,
                                  float* lam_out);
+// kernel B of a reverse step and kernel A of the step before it in one pass:
+// mu_in is the later step's scratch, mu_out this step's
+hipError_t launch_adjoint_fused(int lattice, int nspecies, const Launch& L, const float* mu_in,
+                                float* mu_out, double* gpart);
 hipError_t launch_adjoint_init(int lattice, int nspecies, const LatParams* lp_dev,
                                const LatParams& lp_host, const double* x0, const float* lam0,
                                double* gpart, int nblocks, hipStream_t s);

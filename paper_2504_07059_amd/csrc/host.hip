@@ -784,10 +784,7 @@ lbm_mc_status grad_sum(lbm_mc_ctx* c, int nblocks, double* grad) {
     return LBM_MC_OK;
 }
 
-// kernel A (partials accumulated per tile), kernel B
-lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in,
-                          float* lam_out, hipStream_t stream) {
-    const int ng = c->N * (c->N - 1) / 2 + 3;
+Launch adjoint_launch(lbm_mc_ctx* c, const float* f_prev, hipStream_t stream) {
     Launch L = make_launch(c, f_prev, nullptr, stream);
     L.tiles = c->adj_tiles;
     L.ntiles = L.grid = c->adj_ntiles;
@@ -797,6 +794,14 @@ lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_i
     // state, the two adjoints and the scratch): written-through stores while
     // they fit in the last-level cache
     L.wt = 4 * c->layout.total * (int64_t)sizeof(float) <= ((int64_t)256 << 20) ? 1 : 0;
+    return L;
+}
+
+// kernel A (partials accumulated per tile), kernel B
+lbm_mc_status adjoint_one(lbm_mc_ctx* c, const float* f_prev, const float* lam_in,
+                          float* lam_out, hipStream_t stream) {
+    const int ng = c->N * (c->N - 1) / 2 + 3;
+    const Launch L = adjoint_launch(c, f_prev, stream);
     HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, c->dmu, c->dgpart, ng));
     HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, c->dmu, lam_out));
     return LBM_MC_OK;
@@ -1406,21 +1411,41 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t str
         HIPCHECK(hipMalloc(&c->dlam, (size_t)c->layout.total * sizeof(float)));
         HIPCHECK(hipMemsetAsync(c->dlam, 0, (size_t)c->layout.total * sizeof(float), c->stream));
     }
-    // step k (1..n) reverses the step from states[n-k] and writes lam_out when
-    // n-k is even, the context's buffer otherwise, so the last lands in lam_out
     const int nt = c->adj_ntiles;
     st = grad_clear(c, nt);
     if (st != LBM_MC_OK) return st;
-    st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
-        const float* src = lam_in;
-        for (int64_t k = 1; k <= n; ++k) {
-            float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
-            lbm_mc_status r = adjoint_one(c, states + (n - k) * stride, src, dst, strm);
-            if (r != LBM_MC_OK) return r;
-            src = dst;
-        }
-        return LBM_MC_OK;
-    });
+    if (c->lattice == 0) {
+        // D2Q9: kernel A of the last step, then one fused pass per earlier
+        // step (kernel B of the step after it with kernel A), mu alternating
+        // between the context's two buffers, and kernel B of the first step
+        st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
+            const int ng = c->N * (c->N - 1) / 2 + 3;
+            float* mu[2] = {c->dmu, c->dlam};
+            Launch L = adjoint_launch(c, states + (n - 1) * stride, strm);
+            HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, mu[0], c->dgpart, ng));
+            for (int64_t k = 2; k <= n; ++k) {
+                L = adjoint_launch(c, states + (n - k) * stride, strm);
+                HIPCHECK(launch_adjoint_fused(c->lattice, c->N, L, mu[k % 2], mu[(k - 1) % 2],
+                                              c->dgpart));
+            }
+            HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, mu[(n - 1) % 2], lam_out));
+            return LBM_MC_OK;
+        });
+    } else {
+        // step k (1..n) reverses the step from states[n-k] and writes lam_out
+        // when n-k is even, the context's buffer otherwise, so the last lands
+        // in lam_out
+        st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
+            const float* src = lam_in;
+            for (int64_t k = 1; k <= n; ++k) {
+                float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
+                lbm_mc_status r = adjoint_one(c, states + (n - k) * stride, src, dst, strm);
+                if (r != LBM_MC_OK) return r;
+                src = dst;
+            }
+            return LBM_MC_OK;
+        });
+    }
     if (st != LBM_MC_OK) return st;
     return grad_sum(c, nt, grad);
 }

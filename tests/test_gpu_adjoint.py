@@ -5,8 +5,11 @@ Bars: one reverse step, every adjoint value within 2e-5 of the largest
 (FP32 arithmetic of one step, O(1) adjoint fields); parameter gradients of
 one step within 1e-4 relative (FP64 sums of FP32 node terms); gradients of a
 misfit over hundreds to thousands of steps within 1e-3 relative (FP32 state
-and adjoint along the whole trajectory).  Sequence entry points are
-bit-identical to the single-step ones."""
+and adjoint along the whole trajectory).  The state sequence entry point is
+bit-identical to single steps; the reverse sequence is too in D3Q19, and in
+D2Q9 (where each reverse step's transposed stream runs fused with the next
+one's collision VJP, the adjoint staying in population space) it agrees with
+single reverse steps to FP32 rounding."""
 import json
 import os
 
@@ -212,14 +215,20 @@ def test_adjoint_init_matches_oracle(w):
     _check_grad(got, D.grad.tolist(), g.grad.tolist(), GRAD1_RTOL, 1e-6)
 
 
-def test_sequence_entry_points_equal_single_steps():
-    """replay == step and adjoint_run == repeated adjoint_step, bit for bit,
-    over a sequence with an odd number of steps.  The sequence calls replay
-    captured graphs from their second call on: each is called twice, with
-    other work and a synchronisation in between, and both calls are checked
-    against the single steps."""
-    w = CASES[0]
-    _announce("replay / adjoint_run")
+@pytest.mark.parametrize("case", [0, 4], ids=["d2q9_fused", "d3q19"])
+def test_sequence_entry_points_equal_single_steps(case):
+    """replay == step bit for bit, and adjoint_run == repeated adjoint_step
+    over a sequence with an odd number of steps: bit for bit in D3Q19 and for
+    a one-step run; in D2Q9 (fused reverse steps) within 1e-5 of the largest
+    adjoint value and of the largest gradient term (the fused pass skips the
+    storage transform and its inverse between steps, each a few FP32
+    roundings of O(1) values per step).  The sequence calls replay captured
+    graphs from their second call on: each is called twice, with other work
+    and a synchronisation in between, and both calls are checked against the
+    single steps and against each other."""
+    w = CASES[case]
+    fused = w.lattice == "D2Q9"
+    _announce(f"replay / adjoint_run {w.name}")
     sim = _sim(w)
     n = 7
     s0 = sim.buffers()[0].clone()
@@ -244,14 +253,32 @@ def test_sequence_entry_points_equal_single_steps():
     for k in range(n, 0, -1):
         sim.adjoint_step(seq[k - 1, : sim.total], a, b, g_ref)
         a, b = b, a
+    runs = []
     for rep in range(2):
         g1 = torch.zeros_like(g_ref)
         out_run = torch.zeros_like(s0)
         sim.adjoint_run(seq, n, lam_T, out_run, g1)
         sim.step(3)                     # other work between the two calls
         sim.sync()
-        assert torch.equal(sim.view(out_run), sim.view(a)), rep
-        assert torch.equal(g1, g_ref), rep
+        got, ref = sim.view(out_run), sim.view(a)
+        if fused:
+            assert (got - ref).abs().max().item() <= 1e-5 * ref.abs().max().item(), rep
+            assert (g1 - g_ref).abs().max().item() <= 1e-5 * g_ref.abs().max().item(), rep
+        else:
+            assert torch.equal(got, ref), rep
+            assert torch.equal(g1, g_ref), rep
+        runs.append((got.clone(), g1.clone()))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    # a one-step run is kernel A and kernel B, as adjoint_step
+    g1 = torch.zeros_like(g_ref)
+    g2 = torch.zeros_like(g_ref)
+    out_run = torch.zeros_like(s0)
+    out_step = torch.zeros_like(s0)
+    sim.adjoint_run(seq, 1, lam_T, out_run, g1)
+    sim.adjoint_step(seq[0, : sim.total], lam_T, out_step, g2)
+    sim.sync()
+    assert torch.equal(sim.view(out_run), sim.view(out_step))
+    assert torch.equal(g1, g2)
     sim.close()
 
 
@@ -296,9 +323,11 @@ def test_recorded_states_give_the_checkpointed_gradient():
     """checkpoint_every = 0 records every state in the forward and recomputes
     nothing; the reverse steps then run on the same states as with
     checkpoints (the recomputation is bitwise the forward step): the loss is
-    identical, and the gradient too up to the grouping of its FP64 sums (per
-    segment with checkpoints, once over the run when recorded), also for a
-    run of one step."""
+    identical.  The gradient agrees to FP32 rounding: with checkpoints the
+    adjoint passes through its storage form at each segment boundary, while
+    the recorded run's fused reverse steps keep it in population space, and
+    the FP64 sums are grouped per segment instead of once over the run.  A
+    run of one step (no boundary) agrees to the last digits."""
     import dataclasses
     for steps in (400, 1):
         _announce(f"recorded states 96x4, {steps} steps")
@@ -311,8 +340,9 @@ def test_recorded_states_give_the_checkpointed_gradient():
         for K in (0, None):
             L, dp, dg = _gpu_gradient(ev, dataclasses.replace(prob, checkpoint_every=K), target)
             assert L == L_ref
+            tol = 1e-12 if steps == 1 else 1e-5
             for u, v in zip(dp + dg, dp_ref + dg_ref):
-                assert abs(u - v) <= 1e-12 * scale, (K, u, v)
+                assert abs(u - v) <= tol * scale, (K, u, v)
 
 
 def test_misfit_gradient_full_tube_matches_stored_oracle():
