@@ -11,6 +11,9 @@
 //   kernel B (per node): lam_f(t-1) = S^T mu, i.e. the gather of mu with the
 //            velocities reversed plus the transposed wall terms; stored as
 //            lam_s(t-1) = T^-T lam_f(t-1).
+// In a D2Q9 sequence of reverse steps, kernel B of one step and kernel A of
+// the step before it run as one fused pass that gathers lam_f from the later
+// step's mu directly (T^-T followed by T^T is the identity).
 // Both kernels run one wave per species over tiles of 64 columns (their own
 // tile list, independent of the forward step's execution shape).  The state
 // and adjoint are FP32; parameter gradients are summed in FP64 per thread,
