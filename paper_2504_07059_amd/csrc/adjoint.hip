@@ -72,6 +72,19 @@ struct AdjSplitOp {
     int s, lane;
     bool inside;
     double acc[NG];
+    // 2-D: the layer's mu is stored in the next layer's call, after that
+    // layer's gathers have their loads back
+    static constexpr bool kDefer = Lat<LAT>::DIM == 2;
+    float out[Q];
+    unsigned out_own;
+    bool pend;
+    __device__ __forceinline__ void flush() {
+        if (pend) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) stb<POL>(mu, a, out_own, out[a]);
+        }
+        pend = false;
+    }
     // kernel A alone: lam_f = T^T lam_s(t) from the stored adjoint
     __device__ __forceinline__ void operator()(float P0, float (&F)[Q], int, unsigned own) {
         using L = Lat<LAT>;
@@ -96,6 +109,7 @@ struct AdjSplitOp {
     __device__ __forceinline__ void reverse(float P0, float (&F)[Q], float (&lt)[Q],
                                             unsigned own) {
         using L = Lat<LAT>;
+        if constexpr (kDefer) flush();
         // own density and momentum (sum_a w_a = 1, sum_a c_a w_a = 0)
         float sf = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
@@ -176,8 +190,15 @@ struct AdjSplitOp {
             vjp_finish<LAT, NS>(i, rho, f, C, A, lt, dg);
         }
         if (inside) {
+            if constexpr (kDefer) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) stb<POL>(mu, a, own, lt[a]);
+                for (int a = 0; a < Q; ++a) out[a] = lt[a];
+                out_own = own;
+                pend = true;
+            } else {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) stb<POL>(mu, a, own, lt[a]);
+            }
             int k = 0;
             // every wave holds the same dL/dK: the species-0 wave adds it
 #pragma unroll
@@ -212,10 +233,12 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
           coll_const(P), x1, x2, s, lane, inside, {}};
 #pragma unroll
     for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    op.pend = false;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
     march1<LAT>(species_buf<LAT>(fprev + P.base, P.plane, s), G, s, L, x, y, zero, bx == 64, T.m0,
                 T.m1, op);
+    op.flush();
     block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
@@ -464,6 +487,7 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
           inside, {}};
 #pragma unroll
     for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    op.pend = false;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
     ColGeom g = col_geom<LAT>(G, x, y);
@@ -475,6 +499,7 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     } else {
         march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, NbLoad{});
     }
+    op.flush();
     block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
