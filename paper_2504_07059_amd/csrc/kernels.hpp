@@ -408,18 +408,50 @@ __device__ __forceinline__ void eq_wall_terms(const Buf& B, const GatherConst& G
             }
 }
 
-// Marching state of one heavier species: the marching-axis partial sums of
-// its deviation planes and the reference stencil of layers m-1, m, m+1.
+// Slot of direction a among the directions with a marching-axis component.
 template <int LAT>
+__host__ __device__ constexpr int mar_slot(int a) {
+    int k = 0;
+    for (int b = 1; b < a; ++b) k += Frame<LAT>::pm(b) != 0 ? 1 : 0;
+    return k;
+}
+template <int LAT>
+constexpr int kMarDirs = mar_slot<LAT>(Lat<LAT>::Q);
+
+// Marching state of one heavier species: the marching-axis partial sums of
+// its deviation planes (get/set(k, a): the two sums of direction a) and the
+// reference stencil of layers m-1, m, m+1.
+template <int LAT, bool LDS = false>
 struct Heavy {
     float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
     RhoLayer rl[3];
+    __device__ __forceinline__ float get(int k, int a) const { return k ? acc1[a] : acc0[a]; }
+    __device__ __forceinline__ void set(int k, int a, float v) {
+        if (k)
+            acc1[a] = v;
+        else
+            acc0[a] = v;
+    }
+};
+// The same state with the partial sums in an LDS area of the wave's own
+// ([2 kMarDirs][64] floats, each lane its column; no other lane reads them,
+// so no barrier), so they hold no VGPRs.
+template <int LAT>
+struct Heavy<LAT, true> {
+    float* acc;   // this lane's element of slot 0
+    RhoLayer rl[3];
+    __device__ __forceinline__ float get(int k, int a) const {
+        return acc[(2 * mar_slot<LAT>(a) + k) * 64];
+    }
+    __device__ __forceinline__ void set(int k, int a, float v) {
+        acc[(2 * mar_slot<LAT>(a) + k) * 64] = v;
+    }
 };
 
 // Start the march of a heavier species (planes pb0 .. pb0+Q-1) at layer m0.
-template <int LAT, class NB>
+template <int LAT, class NB, bool HL>
 __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, const ColGeom& g,
-                                            int pb0, const float* L, int m0, Heavy<LAT>& h,
+                                            int pb0, const float* L, int m0, Heavy<LAT, HL>& h,
                                             const NB& nb) {
     using Fr = Frame<LAT>;
     constexpr int Q = Lat<LAT>::Q;
@@ -435,21 +467,21 @@ __device__ __forceinline__ void heavy_begin(const Buf& B, const GatherConst& G, 
             const W3 wmar = wsel(Fr::pm(a), L);
             const float hm = LBM_HP(cm_);
             const float h0 = LBM_HP(c0_);
-            h.acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
-            h.acc1[a] = wmar.m * h0;
-        } else {
-            h.acc0[a] = 0.0f;
-            h.acc1[a] = 0.0f;
+            h.set(0, a, fmaf(wmar.z, h0, wmar.m * hm));
+            h.set(1, a, wmar.m * h0);
+        } else if constexpr (!HL) {
+            h.set(0, a, 0.0f);
+            h.set(1, a, 0.0f);
         }
     }
 }
 
 // One layer of a heavier species: second-order interpolation plus the
 // impermeable-wall terms; side is the column's wall side on the wall axis.
-template <int LAT, bool EQ = false, class NB>
+template <int LAT, bool EQ = false, class NB, bool HL>
 __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, const ColGeom& g,
                                             int pb0, const float* L, unsigned own, unsigned nxt,
-                                            int m, const Sides& sd, Heavy<LAT>& h, float& P0,
+                                            int m, const Sides& sd, Heavy<LAT, HL>& h, float& P0,
                                             float (&F)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
@@ -512,9 +544,10 @@ __device__ __forceinline__ void heavy_layer(const Buf& B, const GatherConst& G, 
         } else {
             const W3 wmar = wsel(Fr::pm(a), L);
             const float hn = LBM_HP(nxt);   // 0 beyond a wall
-            Gv = fmaf(wmar.p, hn, h.acc0[a]);
-            h.acc0[a] = fmaf(wmar.z, hn, h.acc1[a]);
-            h.acc1[a] = wmar.m * hn;
+            const float a0 = h.get(0, a), a1 = h.get(1, a);
+            Gv = fmaf(wmar.p, hn, a0);
+            h.set(0, a, fmaf(wmar.z, hn, a1));
+            h.set(1, a, wmar.m * hn);
         }
         F[a] = fmaf(La::wr(a), delta, Gv);
     }
@@ -606,12 +639,13 @@ __device__ __forceinline__ void march(const Buf (&B)[NS], const GatherConst& G, 
     }
 }
 
-template <int LAT, class NB, class Op>
+template <int LAT, bool HL, class NB, class Op>
 __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, int s,
                                           const float (&L)[3], const ColGeom& g, int m0, int m1,
-                                          Op& op, const NB& nb) {
+                                          Op& op, const NB& nb, float* macc) {
     constexpr int Q = Lat<LAT>::Q;
-    Heavy<LAT> h;
+    Heavy<LAT, HL> h;
+    if constexpr (HL) h.acc = macc;
     if (s > 0) heavy_begin<LAT>(B, G, g, 0, L, m0, h, nb);
     for (int m = m0; m < m1; ++m) {
         const int mp = nbr(m, 1, G.nm, g.wm);
@@ -631,19 +665,21 @@ __device__ __forceinline__ void march1_nb(const Buf& B, const GatherConst& G, in
 // weight triple L; calls op(P0, F, m, own) with the species' values.  With wave_row
 // the wave's 64 lanes are 64 consecutive columns of one row (in order) and the
 // x neighbours are taken across lanes.  lane_zero marks a lane whose reads
-// all return 0.
-template <int LAT, class Op>
+// all return 0.  With HL the marching partial sums live in the LDS area
+// macc (this lane's element of the wave's [2 kMarDirs][64] floats).
+template <int LAT, class Op, bool HL = false>
 __device__ __forceinline__ void march1(const Buf& B, const GatherConst& G, int s,
                                        const float (&L)[3], int x, int y, bool lane_zero,
-                                       bool wave_row, int m0, int m1, Op& op) {
+                                       bool wave_row, int m0, int m1, Op& op,
+                                       float* macc = nullptr) {
     ColGeom g = col_geom<LAT>(G, x, y);
     if (lane_zero) g.colbase += kSolid;
     if (wave_row) {
         const unsigned lane = __lane_id();
         NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
-        march1_nb<LAT>(B, G, s, L, g, m0, m1, op, nb);
+        march1_nb<LAT, HL>(B, G, s, L, g, m0, m1, op, nb, macc);
     } else {
-        march1_nb<LAT>(B, G, s, L, g, m0, m1, op, NbLoad{});
+        march1_nb<LAT, HL>(B, G, s, L, g, m0, m1, op, NbLoad{}, macc);
     }
 }
 

@@ -144,7 +144,10 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // (double-buffered, one barrier per layer), and each wave then forms the
 // mixture and the cross relaxation (identical arithmetic in every wave) and
 // collides and stores its own species.  A wave holds one species' marching
-// state instead of NS, so several times more waves fit on a SIMD.
+// state instead of NS, and keeps its marching-axis partial sums in LDS
+// (2 per direction with a marching component: 12 floats per lane in 2-D, 20
+// in 3-D), so several times more waves fit on a SIMD: five in 2-D, four in
+// 3-D (three with the sums in registers).
 //
 // A work-group may hold W such segments of 64 columns side by side
 // (threadIdx.z = segment; bx * by = 64 W): W consecutive 64-column pieces of
@@ -288,6 +291,9 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
     const int xstride = W * NS * 64;
     float4* xch = smem + seg * NS * 64;
     float4* xgr = smem + 2 * xstride + seg * NS * 64;
+    // this wave's marching partial sums, after the exchange buffers
+    float* macc = reinterpret_cast<float*>(smem + (FRC == 2 ? 2 : 1) * 2 * xstride) +
+                  (seg * NS + s) * 2 * kMarDirs<LAT> * 64 + lane;
     int t0, t1;
     tile_range(ntiles, t0, t1);
     bool bad = false;
@@ -312,8 +318,9 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
                                                 + s * ((int64_t)P.nx * P.ny * P.nz)
                                           : nullptr,
                                  &P, x, y, accel, {}, 0u, false};
-        march1<LAT>(species_buf<LAT>(src + P.base, P.plane, s), G, s, L, x, y, zero,
-                    bx % 64 == 0, T.m0, T.m1, op);
+        march1<LAT, decltype(op), true>(
+                species_buf<LAT>(src + P.base, P.plane, s), G, s, L, x, y, zero, bx % 64 == 0,
+                T.m0, T.m1, op, macc);
         op.flush();
         bad = bad || op.bad;
         __syncthreads();   // the next tile reuses the exchange buffers
@@ -682,7 +689,8 @@ hipError_t launch_step_lat(int ns, const Launch& L) {
             if constexpr (EXT != 3) {   // (the equilibrium boundary has no split form)
                 if (L.split) {
                     const int W = L.bx * L.by / 64;
-                    const size_t lds = (FRC == 2 ? 2 : 1) * 2 * (size_t)W * NS * 64 * sizeof(float4);
+                    const size_t lds = (FRC == 2 ? 2 : 1) * 2 * (size_t)W * NS * 64 * sizeof(float4) +
+                                       (size_t)W * NS * 2 * kMarDirs<LAT> * 64 * sizeof(float);
                     hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, POL>), dim3(L.grid),
                                        dim3(64, NS, W), lds, L.stream, L.src, L.dst, L.lp,
                                        L.tiles, L.ntiles, L.bx, L.dens, L.accel, L.flag);
