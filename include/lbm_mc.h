@@ -359,11 +359,12 @@ lbm_mc_status lbm_mc_replay(lbm_mc_ctx* ctx, const float* src, int64_t n, float*
  * n reverse steps through a stored sequence: states[k] = s(t0 + k) for
  * k = 0..n-1 (layout as lbm_mc_replay), lam_in = lam(t0 + n); on return
  * lam_out = lam(t0) and grad has the n steps' parameter terms added.
- * The arithmetic of n lbm_mc_adjoint_step calls; for D2Q9 the transposed
- * stream of each reverse step runs in one pass with the collision VJP of the
- * step before it, so between steps the adjoint stays in population space
- * (lam_f) instead of going through the storage transform and back, and the
- * results agree with the single steps to FP32 rounding (D3Q19: identical).
+ * The arithmetic of n lbm_mc_adjoint_step calls; the transposed stream of
+ * each reverse step runs in one pass with the collision VJP of the step
+ * before it, so between steps the adjoint stays in population space (lam_f)
+ * instead of going through the storage transform and back, and the results
+ * agree with the single steps to FP32 rounding (D3Q19 with four species:
+ * identical, the steps are not fused there).
  * Uses one more context-owned buffer.  lam_out must not alias lam_in.
  */
 lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t stride,

@@ -11,8 +11,8 @@
 //   kernel B (per node): lam_f(t-1) = S^T mu, i.e. the gather of mu with the
 //            velocities reversed plus the transposed wall terms; stored as
 //            lam_s(t-1) = T^-T lam_f(t-1).
-// In a D2Q9 sequence of reverse steps, kernel B of one step and kernel A of
-// the step before it run as one fused pass that gathers lam_f from the later
+// In a sequence of reverse steps, kernel B of one step and kernel A of the
+// step before it run as one fused pass that gathers lam_f from the later
 // step's mu directly (T^-T followed by T^T is the identity).
 // Both kernels run one wave per species over tiles of 64 columns (their own
 // tile list, independent of the forward step's execution shape).  The state
@@ -72,9 +72,11 @@ struct AdjSplitOp {
     int s, lane;
     bool inside;
     double acc[NG];
-    // 2-D: the layer's mu is stored in the next layer's call, after that
-    // layer's gathers have their loads back
-    static constexpr bool kDefer = Lat<LAT>::DIM == 2;
+    // 2-D, up to three species: the layer's mu is stored in the next layer's
+    // call, after that layer's gathers have their loads back (with four
+    // species the held values would cost the fused pass its second wave per
+    // SIMD)
+    static constexpr bool kDefer = Lat<LAT>::DIM == 2 && NS < 4;
     float out[Q];
     unsigned out_own;
     bool pend;
@@ -268,15 +270,32 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
 
 // Marching state of the reversed gather of one heavier species: the
 // marching-axis partial sums of its planes of mu.
-template <int LAT>
+template <int LAT, bool LDS = false>
 struct RevMarch {
     float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
+    __device__ __forceinline__ float get(int k, int a) const { return k ? acc1[a] : acc0[a]; }
+    __device__ __forceinline__ void set(int k, int a, float v) {
+        if (k)
+            acc1[a] = v;
+        else
+            acc0[a] = v;
+    }
+};
+template <int LAT>
+struct RevMarch<LAT, true> {
+    float* acc;
+    __device__ __forceinline__ float get(int k, int a) const {
+        return acc[(2 * mar_slot<LAT>(a) + k) * 64];
+    }
+    __device__ __forceinline__ void set(int k, int a, float v) {
+        acc[(2 * mar_slot<LAT>(a) + k) * 64] = v;
+    }
 };
 
 // Start the reversed gather of species s (M: its view of mu) at layer m0.
-template <int LAT, class NB>
+template <int LAT, class NB, bool RL>
 __device__ __forceinline__ void rev_begin(const Buf& M, const GatherConst& G, const ColGeom& g,
-                                          int s, const float (&L)[3], int m0, RevMarch<LAT>& r,
+                                          int s, const float (&L)[3], int m0, RevMarch<LAT, RL>& r,
                                           const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
@@ -291,21 +310,21 @@ __device__ __forceinline__ void rev_begin(const Buf& M, const GatherConst& G, co
             const W3 wmar = wsel(-Fr::pm(a), L);
             const float hm = LBM_HPR(cm_);
             const float h0 = LBM_HPR(c0_);
-            r.acc0[a] = fmaf(wmar.z, h0, wmar.m * hm);
-            r.acc1[a] = wmar.m * h0;
-        } else {
-            r.acc0[a] = 0.0f;
-            r.acc1[a] = 0.0f;
+            r.set(0, a, fmaf(wmar.z, h0, wmar.m * hm));
+            r.set(1, a, wmar.m * h0);
+        } else if constexpr (!RL) {
+            r.set(0, a, 0.0f);
+            r.set(1, a, 0.0f);
         }
     }
 }
 
 // lam_f(t-1) at layer m of the column (population space): the reversed
 // gather of mu plus the transposed wall terms.
-template <int LAT, class NB>
+template <int LAT, class NB, bool RL>
 __device__ __forceinline__ void rev_layer(const Buf& M, const GatherConst& G, const ColGeom& g,
                                           int s, const float (&L)[3], int m, unsigned own,
-                                          unsigned nxt, RevMarch<LAT>& r,
+                                          unsigned nxt, RevMarch<LAT, RL>& r,
                                           float (&lf)[Lat<LAT>::Q], const NB& nb) {
     using Fr = Frame<LAT>;
     using La = Lat<LAT>;
@@ -347,9 +366,10 @@ __device__ __forceinline__ void rev_layer(const Buf& M, const GatherConst& G, co
         } else {
             const W3 wmar = wsel(-Fr::pm(a), L);
             const float hn = LBM_HPR(nxt);   // 0 beyond a wall
-            lf[a] = fmaf(wmar.p, hn, r.acc0[a]);
-            r.acc0[a] = fmaf(wmar.z, hn, r.acc1[a]);
-            r.acc1[a] = wmar.m * hn;
+            const float a0 = r.get(0, a), a1 = r.get(1, a);
+            lf[a] = fmaf(wmar.p, hn, a0);
+            r.set(0, a, fmaf(wmar.z, hn, a1));
+            r.set(1, a, wmar.m * hn);
         }
     }
     // transposed wall terms (walls on one axis): the forward adds
@@ -405,10 +425,17 @@ __device__ __forceinline__ void adj_stream_column(const Buf& M, const Buf& O,
 template <int LAT, class NB, class Op>
 __device__ __forceinline__ void march_fused(const Buf& B, const Buf& M, const GatherConst& G,
                                             int s, const float (&L)[3], const ColGeom& g, int m0,
-                                            int m1, Op& op, const NB& nb) {
+                                            int m1, Op& op, const NB& nb, float* macc) {
     constexpr int Q = Lat<LAT>::Q;
-    Heavy<LAT> h;
-    RevMarch<LAT> r;
+    // D3Q19: both marches' partial sums in LDS (20 floats per lane each),
+    // which keeps the fused pass at kernel A's occupancy
+    constexpr bool HL = Lat<LAT>::DIM == 3;
+    Heavy<LAT, HL> h;
+    RevMarch<LAT, HL> r;
+    if constexpr (HL) {
+        h.acc = macc;
+        r.acc = macc + 2 * kMarDirs<LAT> * 64;
+    }
     if (s > 0) heavy_begin<LAT>(B, G, g, 0, L, m0, h, nb);
     rev_begin<LAT>(M, G, g, s, L, m0, r, nb);
     for (int m = m0; m < m1; ++m) {
@@ -474,8 +501,11 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     using Op = AdjSplitOp<LAT, NS, POL>;
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
+    // 3-D: the two marches' partial sums of every wave
+    __shared__ float msum[Lat<LAT>::DIM == 3 ? NS : 1][4 * kMarDirs<LAT>][64];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    float* macc = &msum[Lat<LAT>::DIM == 3 ? s : 0][0][lane];
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
     int x, y;
@@ -495,9 +525,9 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     const Buf B = species_buf<LAT>(fprev + P.base, P.plane, s);
     if (bx == 64) {
         const NbWave nb{lane == 0 ? g.col.bxm : (lane == 63 ? g.col.bxp : 0u)};
-        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, nb);
+        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, nb, macc);
     } else {
-        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, NbLoad{});
+        march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, NbLoad{}, macc);
     }
     op.flush();
     block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
@@ -657,14 +687,17 @@ static hipError_t adjf_t(const Launch& L, const float* mu_in, float* mu_out, dou
     return hipGetLastError();
 }
 
-// D2Q9 only: with D3Q19's marching state the fused kernel would hold one wave
-// per SIMD for three or more species, where kernels A and B hold two and eight
+// D3Q19 with four species is not provided: the fused kernel would hold one
+// wave per SIMD there (256 VGPRs plus AGPRs), and kernels A and B are faster
 hipError_t launch_adjoint_fused(int lattice, int ns, const Launch& L, const float* mu_in,
                                 float* mu_out, double* gpart) {
     if (lattice == 0) {
         if (ns == 2) return adjf_t<0, 2>(L, mu_in, mu_out, gpart);
         if (ns == 3) return adjf_t<0, 3>(L, mu_in, mu_out, gpart);
         if (ns == 4) return adjf_t<0, 4>(L, mu_in, mu_out, gpart);
+    } else {
+        if (ns == 2) return adjf_t<1, 2>(L, mu_in, mu_out, gpart);
+        if (ns == 3) return adjf_t<1, 3>(L, mu_in, mu_out, gpart);
     }
     return hipErrorInvalidValue;
 }

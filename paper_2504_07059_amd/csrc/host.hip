@@ -1414,10 +1414,12 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t str
     const int nt = c->adj_ntiles;
     st = grad_clear(c, nt);
     if (st != LBM_MC_OK) return st;
-    if (c->lattice == 0) {
-        // D2Q9: kernel A of the last step, then one fused pass per earlier
-        // step (kernel B of the step after it with kernel A), mu alternating
-        // between the context's two buffers, and kernel B of the first step
+    if (c->lattice == LBM_MC_D2Q9 || c->N <= 3) {
+        // kernel A of the last step, then one fused pass per earlier step
+        // (kernel B of the step after it with kernel A), mu alternating
+        // between the context's two buffers, and kernel B of the first step;
+        // D3Q19 with four species keeps kernels A and B (see
+        // launch_adjoint_fused)
         st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
             const int ng = c->N * (c->N - 1) / 2 + 3;
             float* mu[2] = {c->dmu, c->dlam};
