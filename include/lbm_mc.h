@@ -363,8 +363,7 @@ lbm_mc_status lbm_mc_replay(lbm_mc_ctx* ctx, const float* src, int64_t n, float*
  * each reverse step runs in one pass with the collision VJP of the step
  * before it, so between steps the adjoint stays in population space (lam_f)
  * instead of going through the storage transform and back, and the results
- * agree with the single steps to FP32 rounding (D3Q19 with four species:
- * identical, the steps are not fused there).
+ * agree with the single steps to FP32 rounding (a one-step run: identical).
  * Uses one more context-owned buffer.  lam_out must not alias lam_in.
  */
 lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* ctx, const float* states, int64_t stride,

@@ -71,7 +71,18 @@ struct AdjSplitOp {
     float (*x2)[KX][64];
     int s, lane;
     bool inside;
-    double acc[NG];
+    // FP64 gradient sums of this lane: in registers in 2-D; in 3-D in LDS
+    // (accl: this lane's element of the wave's [NG][64] doubles), which keeps
+    // the D3Q19 kernels at two waves per SIMD with four species
+    static constexpr bool kLdsSums = Lat<LAT>::DIM == 3;
+    double accr[kLdsSums ? 1 : NG];
+    double* accl;
+    __device__ __forceinline__ double& acc(int q) {
+        if constexpr (kLdsSums)
+            return accl[q * 64];
+        else
+            return accr[q];
+    }
     // 2-D, up to three species: the layer's mu is stored in the next layer's
     // call, after that layer's gathers have their loads back (with four
     // species the held values would cost the fused pass its second wave per
@@ -206,10 +217,15 @@ struct AdjSplitOp {
 #pragma unroll
             for (int i = 0; i < NS; ++i)
 #pragma unroll
-                for (int j = i + 1; j < NS; ++j) acc[k++] += s == 0 ? (double)dK[i][j] : 0.0;
+                for (int j = i + 1; j < NS; ++j, ++k) acc(k) += s == 0 ? (double)dK[i][j] : 0.0;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) acc[k + d] += (double)dg[d];
+            for (int d = 0; d < 3; ++d) acc(k + d) += (double)dg[d];
         }
+    }
+    // the wave's sums, for the block reduction
+    __device__ __forceinline__ void sums(double (&out)[NG]) {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) out[q] = acc(q);
     }
 };
 
@@ -224,6 +240,9 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
     using Op = AdjSplitOp<LAT, NS, POL>;
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
+    __shared__ double gsum[Op::kLdsSums ? NS : 1][Op::NG][64];
+    // 3-D: the march's partial sums of every wave
+    __shared__ float msum[Lat<LAT>::DIM == 3 ? NS - 1 : 1][2 * kMarDirs<LAT>][64];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const Tile T = tiles[blockIdx.x];
@@ -232,16 +251,19 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
     bool zero;
     const bool inside = tile_column<LAT>(T, P, lane, bx, x, y, zero);
     Op op{species_buf<LAT>(lam + P.base, P.plane, s), species_buf<LAT>(mu + P.base, P.plane, s),
-          coll_const(P), x1, x2, s, lane, inside, {}};
+          coll_const(P), x1, x2, s, lane, inside, {}, &gsum[Op::kLdsSums ? s : 0][0][lane]};
 #pragma unroll
-    for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    for (int q = 0; q < Op::NG; ++q) op.acc(q) = 0.0;
     op.pend = false;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
-    march1<LAT>(species_buf<LAT>(fprev + P.base, P.plane, s), G, s, L, x, y, zero, bx == 64, T.m0,
-                T.m1, op);
+    march1<LAT, Op, Lat<LAT>::DIM == 3>(species_buf<LAT>(fprev + P.base, P.plane, s), G, s, L, x,
+                                         y, zero, bx == 64, T.m0, T.m1, op,
+                                         &msum[Lat<LAT>::DIM == 3 && s > 0 ? s - 1 : 0][0][lane]);
     op.flush();
-    block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
+    double sums[Op::NG];
+    op.sums(sums);
+    block_reduce_add<Op::NG>(sums, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
 // ------------------------------------------------------------------ kernel B
@@ -427,8 +449,9 @@ __device__ __forceinline__ void march_fused(const Buf& B, const Buf& M, const Ga
                                             int s, const float (&L)[3], const ColGeom& g, int m0,
                                             int m1, Op& op, const NB& nb, float* macc) {
     constexpr int Q = Lat<LAT>::Q;
-    // D3Q19: both marches' partial sums in LDS (20 floats per lane each),
-    // which keeps the fused pass at kernel A's occupancy
+    // D3Q19: both marches' partial sums in LDS (20 floats per lane each;
+    // species 0, the exact shift, has none), which keeps the fused pass at
+    // two waves per SIMD for up to four species
     constexpr bool HL = Lat<LAT>::DIM == 3;
     Heavy<LAT, HL> h;
     RevMarch<LAT, HL> r;
@@ -502,10 +525,12 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
     // 3-D: the two marches' partial sums of every wave
-    __shared__ float msum[Lat<LAT>::DIM == 3 ? NS : 1][4 * kMarDirs<LAT>][64];
+    __shared__ float msum[Lat<LAT>::DIM == 3 ? NS - 1 : 1][4 * kMarDirs<LAT>][64];
+    __shared__ double gsum[Op::kLdsSums ? NS : 1][Op::NG][64];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-    float* macc = &msum[Lat<LAT>::DIM == 3 ? s : 0][0][lane];
+    // (species 0, the exact shift, keeps no marching state)
+    float* macc = &msum[Lat<LAT>::DIM == 3 && s > 0 ? s - 1 : 0][0][lane];
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
     int x, y;
@@ -514,9 +539,9 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     const Buf M = species_buf<LAT>(mu_in + P.base, P.plane, s);
     // (the op's stored-adjoint view is not read on this path)
     Op op{M, species_buf<LAT>(mu_out + P.base, P.plane, s), coll_const(P), x1, x2, s, lane,
-          inside, {}};
+          inside, {}, &gsum[Op::kLdsSums ? s : 0][0][lane]};
 #pragma unroll
-    for (int q = 0; q < Op::NG; ++q) op.acc[q] = 0.0;
+    for (int q = 0; q < Op::NG; ++q) op.acc(q) = 0.0;
     op.pend = false;
     const GatherConst G = gather_const(P, DIM);
     const float L[3] = {P.lam[s][0], P.lam[s][1], P.lam[s][2]};
@@ -530,7 +555,9 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
         march_fused<LAT>(B, M, G, s, L, g, T.m0, T.m1, op, NbLoad{}, macc);
     }
     op.flush();
-    block_reduce_add<Op::NG>(op.acc, gpart + (int64_t)blockIdx.x * Op::NG);
+    double sums[Op::NG];
+    op.sums(sums);
+    block_reduce_add<Op::NG>(sums, gpart + (int64_t)blockIdx.x * Op::NG);
 }
 
 // ----------------------------------------------------------------- init VJP
@@ -687,8 +714,6 @@ static hipError_t adjf_t(const Launch& L, const float* mu_in, float* mu_out, dou
     return hipGetLastError();
 }
 
-// D3Q19 with four species is not provided: the fused kernel would hold one
-// wave per SIMD there (256 VGPRs plus AGPRs), and kernels A and B are faster
 hipError_t launch_adjoint_fused(int lattice, int ns, const Launch& L, const float* mu_in,
                                 float* mu_out, double* gpart) {
     if (lattice == 0) {
@@ -698,6 +723,7 @@ hipError_t launch_adjoint_fused(int lattice, int ns, const Launch& L, const floa
     } else {
         if (ns == 2) return adjf_t<1, 2>(L, mu_in, mu_out, gpart);
         if (ns == 3) return adjf_t<1, 3>(L, mu_in, mu_out, gpart);
+        if (ns == 4) return adjf_t<1, 4>(L, mu_in, mu_out, gpart);
     }
     return hipErrorInvalidValue;
 }

@@ -1414,40 +1414,22 @@ lbm_mc_status lbm_mc_adjoint_run(lbm_mc_ctx* c, const float* states, int64_t str
     const int nt = c->adj_ntiles;
     st = grad_clear(c, nt);
     if (st != LBM_MC_OK) return st;
-    if (c->lattice == LBM_MC_D2Q9 || c->N <= 3) {
-        // kernel A of the last step, then one fused pass per earlier step
-        // (kernel B of the step after it with kernel A), mu alternating
-        // between the context's two buffers, and kernel B of the first step;
-        // D3Q19 with four species keeps kernels A and B (see
-        // launch_adjoint_fused)
-        st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
-            const int ng = c->N * (c->N - 1) / 2 + 3;
-            float* mu[2] = {c->dmu, c->dlam};
-            Launch L = adjoint_launch(c, states + (n - 1) * stride, strm);
-            HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, mu[0], c->dgpart, ng));
-            for (int64_t k = 2; k <= n; ++k) {
-                L = adjoint_launch(c, states + (n - k) * stride, strm);
-                HIPCHECK(launch_adjoint_fused(c->lattice, c->N, L, mu[k % 2], mu[(k - 1) % 2],
-                                              c->dgpart));
-            }
-            HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, mu[(n - 1) % 2], lam_out));
-            return LBM_MC_OK;
-        });
-    } else {
-        // step k (1..n) reverses the step from states[n-k] and writes lam_out
-        // when n-k is even, the context's buffer otherwise, so the last lands
-        // in lam_out
-        st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
-            const float* src = lam_in;
-            for (int64_t k = 1; k <= n; ++k) {
-                float* dst = (n - k) % 2 == 0 ? lam_out : c->dlam;
-                lbm_mc_status r = adjoint_one(c, states + (n - k) * stride, src, dst, strm);
-                if (r != LBM_MC_OK) return r;
-                src = dst;
-            }
-            return LBM_MC_OK;
-        });
-    }
+    // kernel A of the last step, then one fused pass per earlier step (kernel
+    // B of the step after it with kernel A), mu alternating between the
+    // context's two buffers, and kernel B of the first step
+    st = run_sequence(c, 1, states, lam_in, lam_out, n, stride, [&](hipStream_t strm) {
+        const int ng = c->N * (c->N - 1) / 2 + 3;
+        float* mu[2] = {c->dmu, c->dlam};
+        Launch L = adjoint_launch(c, states + (n - 1) * stride, strm);
+        HIPCHECK(launch_adjoint(c->lattice, c->N, L, lam_in, mu[0], c->dgpart, ng));
+        for (int64_t k = 2; k <= n; ++k) {
+            L = adjoint_launch(c, states + (n - k) * stride, strm);
+            HIPCHECK(launch_adjoint_fused(c->lattice, c->N, L, mu[k % 2], mu[(k - 1) % 2],
+                                          c->dgpart));
+        }
+        HIPCHECK(launch_adjoint_stream(c->lattice, c->N, L, mu[(n - 1) % 2], lam_out));
+        return LBM_MC_OK;
+    });
     if (st != LBM_MC_OK) return st;
     return grad_sum(c, nt, grad);
 }
