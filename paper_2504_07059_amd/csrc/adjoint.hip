@@ -293,26 +293,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const float* __restrict__ f
 // Marching state of the reversed gather of one heavier species: the
 // marching-axis partial sums of its planes of mu.
 template <int LAT, bool LDS = false>
-struct RevMarch {
-    float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
-    __device__ __forceinline__ float get(int k, int a) const { return k ? acc1[a] : acc0[a]; }
-    __device__ __forceinline__ void set(int k, int a, float v) {
-        if (k)
-            acc1[a] = v;
-        else
-            acc0[a] = v;
-    }
-};
-template <int LAT>
-struct RevMarch<LAT, true> {
-    float* acc;
-    __device__ __forceinline__ float get(int k, int a) const {
-        return acc[(2 * mar_slot<LAT>(a) + k) * 64];
-    }
-    __device__ __forceinline__ void set(int k, int a, float v) {
-        acc[(2 * mar_slot<LAT>(a) + k) * 64] = v;
-    }
-};
+using RevMarch = MarchSums<LAT, LDS>;
 
 // Start the reversed gather of species s (M: its view of mu) at layer m0.
 template <int LAT, class NB, bool RL>

@@ -418,13 +418,11 @@ __host__ __device__ constexpr int mar_slot(int a) {
 template <int LAT>
 constexpr int kMarDirs = mar_slot<LAT>(Lat<LAT>::Q);
 
-// Marching state of one heavier species: the marching-axis partial sums of
-// its deviation planes (get/set(k, a): the two sums of direction a) and the
-// reference stencil of layers m-1, m, m+1.
+// The two marching-axis partial sums of every direction with a marching
+// component (get/set(k, a): sum k of direction a), in registers.
 template <int LAT, bool LDS = false>
-struct Heavy {
+struct MarchSums {
     float acc0[Lat<LAT>::Q], acc1[Lat<LAT>::Q];
-    RhoLayer rl[3];
     __device__ __forceinline__ float get(int k, int a) const { return k ? acc1[a] : acc0[a]; }
     __device__ __forceinline__ void set(int k, int a, float v) {
         if (k)
@@ -433,19 +431,25 @@ struct Heavy {
             acc0[a] = v;
     }
 };
-// The same state with the partial sums in an LDS area of the wave's own
-// ([2 kMarDirs][64] floats, each lane its column; no other lane reads them,
-// so no barrier), so they hold no VGPRs.
+// The same sums in an LDS area of the wave's own ([2 kMarDirs][64] floats,
+// each lane its column; no other lane reads them, so no barrier), so they
+// hold no VGPRs.
 template <int LAT>
-struct Heavy<LAT, true> {
+struct MarchSums<LAT, true> {
     float* acc;   // this lane's element of slot 0
-    RhoLayer rl[3];
     __device__ __forceinline__ float get(int k, int a) const {
         return acc[(2 * mar_slot<LAT>(a) + k) * 64];
     }
     __device__ __forceinline__ void set(int k, int a, float v) {
         acc[(2 * mar_slot<LAT>(a) + k) * 64] = v;
     }
+};
+
+// Marching state of one heavier species: the marching-axis partial sums of
+// its deviation planes and the reference stencil of layers m-1, m, m+1.
+template <int LAT, bool LDS = false>
+struct Heavy : MarchSums<LAT, LDS> {
+    RhoLayer rl[3];
 };
 
 // Start the march of a heavier species (planes pb0 .. pb0+Q-1) at layer m0.
