@@ -84,24 +84,27 @@ def _timed_steps(sim, steps, warmup):
 # ------------------------------------------------------------------ roofline
 KERNEL_SOURCES = ("step_impl.hpp", "kernels.hpp", "collide.hpp", "lattice.hpp", "common.hpp",
                   "host.hip")
+# the reverse step's kernels (the fused pass) read the forward gather as well
+ADJOINT_SOURCES = KERNEL_SOURCES + ("adjoint.hip", "adjoint.hpp")
 
 
-def kernel_sources_sha():
+def kernel_sources_sha(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2504_07059_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name, tuning):
-    """HBM bytes per launch of the fused step from the committed counter
-    summaries (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one was taken for
-    this workload and execution shape from the current kernel sources; else
-    None."""
+def measured_traffic(workload_name, tuning, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of the dominant kernel (the fused step; the fused
+    reverse pass for an adjoint workload, tuning "reverse") from the committed
+    counter summaries (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one was
+    taken for this workload and execution shape from the current kernel
+    sources; else None."""
     import glob
-    sha = kernel_sources_sha()
+    sha = kernel_sources_sha(sources)
     want = ",".join(str(v) for v in tuning)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
@@ -115,12 +118,13 @@ def measured_traffic(workload_name, tuning):
     return None
 
 
-def roofline(name, per_launch_bytes, ms, steps, tuning=None, ceiling=None, bound="hbm"):
+def roofline(name, per_launch_bytes, ms, steps, tuning=None, ceiling=None, bound="hbm",
+             sources=KERNEL_SOURCES):
     avg_s = ms * 1e-3 / steps
     achieved = per_launch_bytes / avg_s / 1e9
     out = {"bound": bound, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": achieved / PEAK_HBM_GBS,
-           "traffic": measured_traffic(name, tuning) if tuning is not None else None,
+           "traffic": measured_traffic(name, tuning, sources) if tuning is not None else None,
            "bytes_per_launch": per_launch_bytes, "avg_launch_us": avg_s * 1e6}
     if ceiling:
         out["ceiling"] = {"kernel": "lbm_mc_stream_copy", "GBs": ceiling,
@@ -395,7 +399,9 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
            "replay_us_per_step": replay_us, "reverse_us_per_step": reverse_us,
            # one forward step of the gradient: forward, recomputation, reverse
            "fwd_bwd_kernel_us_per_step": fwd_us + replay_us + reverse_us,
-           "reverse_roofline": roofline(None, 108 * species_nodes, reverse_us * 1e-3, 1),
+           "reverse_roofline": roofline(f"adjoint_tube_{nx}x{ny}", 108 * species_nodes,
+                                        reverse_us * 1e-3, 1, tuning=("reverse",),
+                                        sources=ADJOINT_SOURCES),
            "fwd_bwd_roofline": roofline(None, 252 * species_nodes,
                                         (fwd_us + replay_us + reverse_us) * 1e-3, 1)}
     out["fwd_bwd_kernel_over_forward"] = out["fwd_bwd_kernel_us_per_step"] / fwd_us
