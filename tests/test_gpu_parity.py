@@ -177,6 +177,25 @@ def test_execution_shape_does_not_change_results(tuning):
         assert ((c - b).abs().max() / c.abs().max()).item() < F_RTOL
 
 
+@pytest.mark.parametrize("tuning", [(64, 1, 5, 0, 1), (64, 1, 3, 40, 1), (32, 2, 4, 0, 1),
+                                    (16, 4, 7, 40, 1)])
+def test_execution_shape_does_not_change_results_3d(tuning):
+    """The same shape invariance for the species-split D3Q19 step, whose
+    waves keep their marching partial sums in LDS: a persistent grid (a
+    work-group marches several tiles in turn, reusing its LDS areas) and
+    column blocks that are not x rows (x neighbours read from memory instead
+    of across lanes) give bit-identical populations."""
+    w = SMALL[4]
+    _announce(f"{w.name} tuning {tuning}")
+    ref, _, _ = _gpu_run(w, 9, tuning=(64, 1, 4, 0, 1))
+    a = populations(ref, "cur").clone()
+    ref.close()
+    sim, _, _ = _gpu_run(w, 9, tuning=tuning)
+    b = populations(sim)
+    sim.close()
+    assert torch.equal(a, b)
+
+
 def test_determinism_and_resume_are_bitwise():
     w = SMALL[4]
     _announce(f"{w.name} resume")
