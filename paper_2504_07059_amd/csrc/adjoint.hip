@@ -71,10 +71,16 @@ struct AdjSplitOp {
     float (*x2)[KX][64];
     int s, lane;
     bool inside;
-    // FP64 gradient sums of this lane: in registers in 2-D; in 3-D in LDS
-    // (accl: this lane's element of the wave's [NG][64] doubles), which keeps
-    // the D3Q19 kernels at two waves per SIMD with four species
-    static constexpr bool kLdsSums = Lat<LAT>::DIM == 3;
+    // Build of the fused pass for three waves per SIMD: 2-D, up to three
+    // species, states beyond the last-level cache (non-temporal stores).
+    // Its marching and gradient sums then live in LDS and its stores are not
+    // deferred; on cache-resident lattices, where one tile's chain sets the
+    // step time, the register build is faster.
+    static constexpr bool kThree = Lat<LAT>::DIM == 2 && NS <= 3 && POL == kStoreNT;
+    // FP64 gradient sums of this lane: in registers, or in LDS (accl: this
+    // lane's element of the wave's [NG][64] doubles) in 3-D, which keeps the
+    // D3Q19 kernels at two waves per SIMD with four species, and for kThree
+    static constexpr bool kLdsSums = Lat<LAT>::DIM == 3 || kThree;
     double accr[kLdsSums ? 1 : NG];
     double* accl;
     __device__ __forceinline__ double& acc(int q) {
@@ -87,7 +93,7 @@ struct AdjSplitOp {
     // call, after that layer's gathers have their loads back (with four
     // species the held values would cost the fused pass its second wave per
     // SIMD)
-    static constexpr bool kDefer = Lat<LAT>::DIM == 2 && NS < 4;
+    static constexpr bool kDefer = Lat<LAT>::DIM == 2 && NS < 4 && !kThree;
     float out[Q];
     unsigned out_own;
     bool pend;
@@ -430,10 +436,10 @@ __device__ __forceinline__ void march_fused(const Buf& B, const Buf& M, const Ga
                                             int s, const float (&L)[3], const ColGeom& g, int m0,
                                             int m1, Op& op, const NB& nb, float* macc) {
     constexpr int Q = Lat<LAT>::Q;
-    // D3Q19: both marches' partial sums in LDS (20 floats per lane each;
+    // both marches' partial sums in LDS in 3-D (20 floats per lane each;
     // species 0, the exact shift, has none), which keeps the fused pass at
-    // two waves per SIMD for up to four species
-    constexpr bool HL = Lat<LAT>::DIM == 3;
+    // two waves per SIMD for up to four species, and for Op::kThree
+    constexpr bool HL = Lat<LAT>::DIM == 3 || Op::kThree;
     Heavy<LAT, HL> h;
     RevMarch<LAT, HL> r;
     if constexpr (HL) {
@@ -495,7 +501,9 @@ __global__ void __launch_bounds__(256) k_adj_stream(const float* __restrict__ mu
 // so the storage transform and its inverse drop out, and mu(t) goes to mu_out.
 // The parameter gradients accumulate as in kernel A.
 template <int LAT, int NS, int POL>
-__global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fprev,
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(AdjSplitOp<LAT, NS, POL>::kThree ? 3 : 1)))
+    k_adj_fused(const float* __restrict__ fprev,
                                                    const float* __restrict__ mu_in,
                                                    float* __restrict__ mu_out,
                                                    const LatParams* __restrict__ lps,
@@ -505,13 +513,15 @@ __global__ void __launch_bounds__(256) k_adj_fused(const float* __restrict__ fpr
     using Op = AdjSplitOp<LAT, NS, POL>;
     __shared__ float x1[NS][4][64];
     __shared__ float x2[NS][Op::KX][64];
-    // 3-D: the two marches' partial sums of every wave
-    __shared__ float msum[Lat<LAT>::DIM == 3 ? NS - 1 : 1][4 * kMarDirs<LAT>][64];
+    // the two marches' partial sums of every wave (3-D and the three-wave
+    // build)
+    constexpr bool HL = Lat<LAT>::DIM == 3 || Op::kThree;
+    __shared__ float msum[HL ? NS - 1 : 1][HL ? 4 * kMarDirs<LAT> : 1][64];
     __shared__ double gsum[Op::kLdsSums ? NS : 1][Op::NG][64];
     const int lane = (int)threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     // (species 0, the exact shift, keeps no marching state)
-    float* macc = &msum[Lat<LAT>::DIM == 3 && s > 0 ? s - 1 : 0][0][lane];
+    float* macc = &msum[HL && s > 0 ? s - 1 : 0][0][lane];
     const Tile T = tiles[blockIdx.x];
     const LatParams& P = lps[T.lat];
     int x, y;
