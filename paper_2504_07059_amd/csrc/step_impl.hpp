@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(256) k_step(const float* __restrict__ src, flo
 // collides and stores its own species.  A wave holds one species' marching
 // state instead of NS, and keeps its marching-axis partial sums in LDS
 // (2 per direction with a marching component: 12 floats per lane in 2-D, 20
-// in 3-D), so several times more waves fit on a SIMD: five in 2-D, four in
-// 3-D (three with the sums in registers).
+// in 3-D; see kSplitLdsMarch), so several times more waves fit on a SIMD:
+// five in 2-D, four in 3-D (three with the sums in registers).
 //
 // A work-group may hold W such segments of 64 columns side by side
 // (threadIdx.z = segment; bx * by = 64 W): W consecutive 64-column pieces of
@@ -270,6 +270,13 @@ struct SplitOp {
     }
 };
 
+// Where the species-split step keeps its marching partial sums: in LDS,
+// except for 2-D states held in the last-level cache (written-through
+// stores), where one tile's chain sets the step time and registers are
+// faster (6.23 against 6.31 us per step on the 1024x64 tube).
+template <int LAT, int POL>
+constexpr bool kSplitLdsMarch = Lat<LAT>::DIM == 3 || POL != kStoreWT;
+
 // Work-group size limit of the species-split kernels: NS x W waves of 64
 // lanes with W <= 4 and NS x W <= 12 (three waves per SIMD).
 constexpr int kSplitMaxThreads = 768;
@@ -291,7 +298,8 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
     const int xstride = W * NS * 64;
     float4* xch = smem + seg * NS * 64;
     float4* xgr = smem + 2 * xstride + seg * NS * 64;
-    // this wave's marching partial sums, after the exchange buffers
+    // this wave's marching partial sums (when kept in LDS), after the
+    // exchange buffers
     float* macc = reinterpret_cast<float*>(smem + (FRC == 2 ? 2 : 1) * 2 * xstride) +
                   (seg * NS + s) * 2 * kMarDirs<LAT> * 64 + lane;
     int t0, t1;
@@ -318,7 +326,7 @@ __global__ void __launch_bounds__(kSplitMaxThreads) k_step_split(
                                                 + s * ((int64_t)P.nx * P.ny * P.nz)
                                           : nullptr,
                                  &P, x, y, accel, {}, 0u, false};
-        march1<LAT, decltype(op), true>(
+        march1<LAT, decltype(op), kSplitLdsMarch<LAT, POL>>(
                 species_buf<LAT>(src + P.base, P.plane, s), G, s, L, x, y, zero, bx % 64 == 0,
                 T.m0, T.m1, op, macc);
         op.flush();
@@ -690,7 +698,9 @@ hipError_t launch_step_lat(int ns, const Launch& L) {
                 if (L.split) {
                     const int W = L.bx * L.by / 64;
                     const size_t lds = (FRC == 2 ? 2 : 1) * 2 * (size_t)W * NS * 64 * sizeof(float4) +
-                                       (size_t)W * NS * 2 * kMarDirs<LAT> * 64 * sizeof(float);
+                                       (kSplitLdsMarch<LAT, POL>
+                                            ? (size_t)W * NS * 2 * kMarDirs<LAT> * 64 * sizeof(float)
+                                            : 0);
                     hipLaunchKernelGGL((k_step_split<LAT, NS, FRC, EXT, POL>), dim3(L.grid),
                                        dim3(64, NS, W), lds, L.stream, L.src, L.dst, L.lp,
                                        L.tiles, L.ntiles, L.bx, L.dens, L.accel, L.flag);
