@@ -277,6 +277,43 @@ def test_sequence_entry_points_equal_single_steps(case):
     sim.close()
 
 
+def test_sequence_beyond_the_cache_equals_single_steps():
+    """A ternary tube of 1024x640 nodes, whose four population-sized buffers
+    of the reverse step (283 MB) exceed the 256 MB last-level cache: the
+    reverse kernels store non-temporally and the fused pass runs its build
+    for three waves per SIMD (marching and gradient sums in LDS).  A
+    sequence of 5 reverse steps against single reverse steps (kernels A and
+    B): within 1e-5 of the largest adjoint value and of the largest gradient
+    term, as for the cache-resident builds."""
+    _, ev = W.adjoint_tube(nx=1024, ny=640, steps=5)
+    _announce("adjoint_run 1024x640 (beyond the last-level cache)")
+    lbm = _lbm()
+    sim = lbm.LbmMc(lbm.params_from_workload(ev), ev.x0())
+    n = 5
+    s0 = sim.buffers()[0].clone()
+    assert 4 * sim.total * 4 > (256 << 20)
+    stride = (sim.total + 63) // 64 * 64
+    seq = torch.zeros((n + 1, stride), dtype=torch.float32, device=s0.device)
+    seq[0, : sim.total].copy_(s0)
+    sim.replay(seq[0], n, seq[1:])
+    gen = torch.Generator().manual_seed(5)
+    lam_T = torch.zeros_like(s0)
+    sim.view(lam_T).copy_(torch.randn(tuple(sim.view(s0).shape), generator=gen))
+    g_ref = torch.zeros(3 + 3, dtype=torch.float64, device=s0.device)
+    a, b = lam_T.clone(), torch.zeros_like(s0)
+    for k in range(n, 0, -1):
+        sim.adjoint_step(seq[k - 1, : sim.total], a, b, g_ref)
+        a, b = b, a
+    g1 = torch.zeros_like(g_ref)
+    out_run = torch.zeros_like(s0)
+    sim.adjoint_run(seq, n, lam_T, out_run, g1)
+    sim.sync()
+    got, ref = sim.view(out_run), sim.view(a)
+    assert (got - ref).abs().max().item() <= 1e-5 * ref.abs().max().item()
+    assert (g1 - g_ref).abs().max().item() <= 1e-5 * g_ref.abs().max().item()
+    sim.close()
+
+
 def _tube_problem(nx, ny, steps, K):
     adj = _adj()
     truth, ev = W.adjoint_tube(nx=nx, ny=ny, steps=steps)
