@@ -456,6 +456,51 @@ def time_adjoint(nx=512, ny=64, steps=4000, K=100, fwd_bwd=True):
     return out
 
 
+def time_adjoint_3d(K=20):
+    """Reverse sweeps of D3Q19 lattices: a ternary box 256x128x64 with z
+    walls (the adjoint tube's gases) and the 3-D layer workload (four
+    species, 256x128x128): K recorded states, then K reverse steps through
+    lbm_mc_adjoint_run (fused passes), against a forward step."""
+    import torch
+    import lbm_workloads as W
+    from paper_2504_07059_amd import lbm
+    cases = [("adjoint_d3q19_ternary_256x128x64",
+              W.Workload("adjoint_d3q19_ternary", "D3Q19", 256, 128, 64, [2.0, 28.0, 44.0],
+                         W.pairs_to_matrix(W.load_accepted()["ternary_gravity"]["pairs"], 3),
+                         1.0, [0.0, 0.0, -1e-6], [False, False, True], K, "halves")),
+             ("adjoint_layer_mixing_3d_256x128x128", workload("c2"))]
+    out = {}
+    for name, w in cases:
+        sim = lbm.LbmMc(lbm.params_from_workload(w), w.x0())
+        stride = (sim.total + 63) // 64 * 64
+        seq = torch.zeros((K + 1, stride), dtype=torch.float32, device="cuda")
+        seq[0, : sim.total].copy_(sim.buffers()[0])
+        sim.replay(seq[0], K, seq[1:])
+        lam_a = torch.zeros(sim.total, dtype=torch.float32, device="cuda")
+        sim.view(lam_a).fill_(1e-3)
+        lam_b = torch.zeros_like(lam_a)
+        N = w.n_species
+        grad = torch.zeros(N * (N - 1) // 2 + 3, dtype=torch.float64, device="cuda")
+        sim.adjoint_run(seq, K, lam_a, lam_b, grad)      # warm (captures its graph)
+        e0, e1 = _events()
+        torch.cuda.synchronize()
+        e0.record(sim.stream)
+        sim.adjoint_run(seq, K, lam_a, lam_b, grad)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        reverse_us = e0.elapsed_time(e1) * 1e3 / K
+        fwd_us = _timed_steps(sim, 50, 5) * 1e3 / 50
+        species_nodes = w.nx * w.ny * w.nz * N
+        sim.close()
+        del seq
+        torch.cuda.empty_cache()
+        # a D3Q19 reverse step reads f~(t-1) and mu, writes mu: 3 x 19 floats
+        out[name] = {"steps": K, "species_nodes": species_nodes, "reverse_us_per_step": reverse_us,
+                     "forward_us_per_step": fwd_us, "reverse_over_forward": reverse_us / fwd_us,
+                     "reverse_roofline": roofline(None, 228 * species_nodes, reverse_us * 1e-3, 1)}
+    return out
+
+
 # -------------------------------------------------------------- CPU baseline
 def cpu_model():
     try:
@@ -597,7 +642,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the 10,000-step gate")
     ap.add_argument("--tuning", help="fixed execution shape bx,by,rows,persistent,variant")
     ap.add_argument("--only", choices=["batched", "batched_per_lattice", "tube_hbm", "tube_llc",
-                                       "layer_3d", "adjoint", "adjoint_hbm", "copy"],
+                                       "layer_3d", "adjoint", "adjoint_hbm", "adjoint_3d",
+                                       "copy"],
                     help="run one leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -623,6 +669,8 @@ def main():
             res = sub_tube_llc(tuning=fixed)
         elif args.only == "layer_3d":
             res = sub_layer_3d(None, tuning=fixed)
+        elif args.only == "adjoint_3d":
+            res = time_adjoint_3d()
         elif args.only == "adjoint":
             res = time_adjoint()
         else:
@@ -673,6 +721,7 @@ def main():
         sub["layer_3d_256x128x128"] = sub_layer_3d(copy["best_GBs"])
         sub["adjoint_512x64"] = time_adjoint()
         sub["adjoint_4096x1024"] = time_adjoint(4096, 1024, 200, 100, fwd_bwd=False)
+        sub["adjoint_d3q19"] = time_adjoint_3d()
         sub["stream_copy"] = copy
         line["sub"] = sub
     if not args.no_cpu:
