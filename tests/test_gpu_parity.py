@@ -196,6 +196,23 @@ def test_execution_shape_does_not_change_results_3d(tuning):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("tuning", [(128, 1, 8, 0, 1), (64, 1, 5, 40, 1), (256, 1, 3, 0, 1)])
+def test_execution_shape_beyond_the_cache_does_not_change_results(tuning):
+    """A 2-D lattice whose two buffers (2 x 243 MB) exceed the 256 MB
+    last-level cache runs the build with the marching sums in LDS and
+    non-temporal stores: segmented work-groups and a persistent grid give
+    bit-identical populations there too."""
+    w = dataclasses.replace(SMALL[0], name="tube_2048x1100", nx=2048, ny=1100, steps=5)
+    _announce(f"{w.name} tuning {tuning}")
+    ref, _, _ = _gpu_run(w, 5, tuning=(64, 1, 8, 0, 1))
+    assert 2 * ref.total * 4 > (256 << 20)
+    a = ref.raw("cur").clone()
+    ref.close()
+    sim, _, _ = _gpu_run(w, 5, tuning=tuning)
+    assert torch.equal(a, sim.raw("cur"))
+    sim.close()
+
+
 def test_determinism_and_resume_are_bitwise():
     w = SMALL[4]
     _announce(f"{w.name} resume")
