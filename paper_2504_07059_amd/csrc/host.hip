@@ -523,8 +523,10 @@ lbm_mc_status build_tiles(lbm_mc_ctx* c) {
                     t.lat = l;
                     t.x0 = xb * T.bx;
                     t.y0 = yb * T.by;
-                    t.m0 = mc * T.rows;
-                    t.m1 = std::min(nm, (mc + 1) * T.rows);
+                    // the layers split evenly over the column's nmc tiles
+                    // (at most T.rows each): no short last tile
+                    t.m0 = (int)((int64_t)mc * nm / nmc);
+                    t.m1 = (int)((int64_t)(mc + 1) * nm / nmc);
                     c->htiles.push_back(t);
                 }
         c->hlp[l].tile_end = (int)c->htiles.size();
